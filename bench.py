@@ -1,0 +1,255 @@
+"""Benchmark of the particle-phase step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3-1m]
+
+One "step" is prs_step_particles on the whole bed: clear the force field,
+sort the spheres into cells, multi-direct forcing (interpolate + spread per
+iteration), collision search and n_sub contact/Newton-Euler substeps, and the
+write-back.  Inputs are synthetic and resident in HBM before timing starts.
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-step/s, markers/s, contacts/s; FP32+learned vs FP64 plain at 1e-6 slip"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def params_for(P, W, w, precision, **kw):
+    ph = W.PHYS
+    nx, ny, nz = w.grid
+    d = dict(nx=nx, ny=ny, nz=nz, h=w.h, radius=0.5 * ph["D"], rho_p=ph["rho_p"],
+             rho_f=ph["rho_f"], gravity=ph["g"], n_markers=w.n_markers, dt_f=ph["dt_f"],
+             alpha=ph["alpha"], n_iter=w.n_iter, n_sub=ph["n_sub"], k_n=ph["k_n"], e_n=ph["e_n"],
+             mu=ph["mu"], kt_ratio=ph["kt_ratio"], dt_ratio=ph["dt_ratio"], skin=0.1,
+             precision=precision, max_particles=w.n)
+    d.update(kw)
+    return P.make_params(**d)
+
+
+def touched_nodes(ctx, x, torch):
+    """Grid nodes per component inside at least one marker stencil (spread of
+    positive unit forces; every node in a stencil gets a positive weight)."""
+    n = x.shape[0]
+    F = torch.ones((n, ctx.p.n_markers, 3), dtype=ctx.dtype, device="cuda")
+    f = [torch.zeros(s, dtype=ctx.dtype, device="cuda") for s in ctx.grid_shapes()]
+    ctx.spread(x, F, f, accumulate=False)
+    torch.cuda.synchronize()
+    out = [int(torch.count_nonzero(a)) for a in f]
+    del F, f
+    torch.cuda.empty_cache()
+    return out
+
+
+def ib_bytes(w, n_touched, s):
+    """Algorithmic bytes of one interpolation and one spreading pass.
+
+    interpolation: read u-hat and f at every touched node (2 s per node and
+    component), write the marker correction (3 s per marker), read the sphere
+    state (9 doubles) and write the slip partials (2 doubles) per sphere.
+    spreading: read the correction (3 s per marker), read-modify-write f at
+    every touched node (2 s), read-modify-write the 12 force/torque
+    accumulators per sphere."""
+    M = w.n * w.n_markers
+    NT = sum(n_touched)
+    interp = NT * 2 * s + M * 3 * s + w.n * (9 + 2) * 8
+    spread = M * 3 * s + NT * 2 * s + w.n * 3 * 8 + w.n * 12 * 8 * 2
+    return interp, spread
+
+
+def run_form(P, W, w, bed, precision, steps, warmup, torch, measure_touched=False):
+    import numpy as np
+
+    dt = torch.float32 if precision == P.F32 else torch.float64
+    modes = W.flow_modes(w, bed.bed_top)
+    t0 = time.time()
+    uhat = W.fluid_field(w, modes, device="cuda", dtype=dt)
+    log(f"field ({dt}) generated in {time.time() - t0:.1f}s")
+    f = [torch.zeros_like(a) for a in uhat]
+    x0 = torch.as_tensor(bed.x, device="cuda")
+    u0 = torch.as_tensor(bed.u, device="cuda")
+    om0 = torch.as_tensor(bed.om, device="cuda")
+    res = {}
+    with P.Context(params_for(P, W, w, precision)) as ctx:
+        if measure_touched:
+            res["touched"] = touched_nodes(ctx, x0, torch)
+            log(f"touched nodes per component: {res['touched']}")
+        x, u, om = x0.clone(), u0.clone(), om0.clone()
+        H = P.History.zeros(w.n)
+        Fh = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+        Th = torch.empty_like(Fh)
+        for k in range(warmup):
+            _, _, st = ctx.step(uhat, f, x, u, om, H, Fh, Th, zero_f=True)
+            log(f"warmup {k + 1}/{warmup}: iterations {st['iterations']} slip {st['rel_slip']}")
+        ctx.timing(True)
+        ctx.read_timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        contacts = 0
+        for k in range(steps):
+            _, _, st = ctx.step(uhat, f, x, u, om, H, Fh, Th, zero_f=True)
+            contacts += st["contacts"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = ctx.read_timing(reset=True)
+        ctx.timing(False)
+        log(f"{steps} timed steps in {wall:.3f}s; last stats {st}")
+    res.update(wall=wall, timing=tm, stats=st, contacts=contacts)
+    del uhat, f
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(W, w, bed, width=12.0):
+    """The FP64 oracle, single-threaded, on a window of the same bed: the
+    spheres with centres in a width x Ly x width column, the fluid field on
+    that column plus a margin (synthetic field in FP64), one full step."""
+    import numpy as np
+
+    import oracle
+
+    ph = W.PHYS
+    nx, ny, nz = w.grid
+    h = w.h
+    x0 = 0.5 * (w.domain[0] - width)
+    z0 = 0.5 * (w.domain[2] - width)
+    sel = ((bed.x[:, 0] >= x0) & (bed.x[:, 0] < x0 + width) &
+           (bed.x[:, 2] >= z0) & (bed.x[:, 2] < z0 + width))
+    xs, us, oms = (np.ascontiguousarray(a[sel]) for a in (bed.x, bed.u, bed.om))
+    margin = 1.0
+    wi0 = int(math.floor((x0 - margin) / h))
+    wk0 = int(math.floor((z0 - margin) / h))
+    wnx = int(math.ceil((width + 2 * margin) / h))
+    wnz = wnx
+    # the same generator, evaluated on the window's node columns only (host, FP64)
+    modes = W.flow_modes(w, bed.bed_top)
+    uh = [np.ascontiguousarray(t.numpy())
+          for t in W.fluid_field(w, modes, window=(wi0, wnx, wk0, wnz))]
+    po = oracle.make_params(nx=nx, ny=ny, nz=nz, h=h, wi0=wi0 % nx, wnx=wnx, wk0=wk0 % nz,
+                            wnz=wnz, R=0.5 * ph["D"], nl=w.n_markers, g=ph["g"],
+                            rho_p=ph["rho_p"], rho_f=ph["rho_f"], dt_f=ph["dt_f"],
+                            alpha=ph["alpha"], n_iter=w.n_iter, n_sub=ph["n_sub"], k_n=ph["k_n"],
+                            e_n=ph["e_n"], mu=ph["mu"], kt_ratio=ph["kt_ratio"],
+                            dt_ratio=ph["dt_ratio"], use_cells=1)
+    f = [np.zeros_like(a) for a in uh]
+    H = oracle.History(len(xs))
+    t0 = time.perf_counter()
+    rc, out = oracle.step(po, uh, f, xs, us, oms, H)
+    t = time.perf_counter() - t0
+    return dict(value=len(xs) / t, unit="particle-step/s", cores=1, kind="oracle",
+                sample=(f"{len(xs)} spheres ({len(xs) * w.n_markers} markers) with centres in a "
+                        f"{width:g}D x {w.domain[1]:g}D x {width:g}D column of the same bed, "
+                        f"one full step ({w.n_iter} forcing iterations, {ph['n_sub']} substeps), "
+                        f"FP64, {t:.1f}s"), rc=rc)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3-1m")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "form of the particle step is a design in DESIGN.md, not built", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2108_01814_amd as P
+    from paper_2108_01814_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    P.lib()
+    w = W.WORKLOADS[args.workload]
+    t0 = time.time()
+    bed = W.make_bed(w)
+    log(f"{w.name}: {w.n} spheres, grid {w.grid}, bed generated in {time.time() - t0:.1f}s")
+
+    r32 = run_form(P, W, w, bed, P.F32, args.steps, args.warmup, torch, measure_touched=True)
+    K = args.steps
+    tm = r32["timing"]
+    t_step = r32["wall"] / K
+    M = w.n * w.n_markers
+    iters = r32["stats"]["iterations"]
+    t_ib = (tm["ms_interp"] + tm["ms_spread"]) / 1e3 / K
+    t_dem = (tm["ms_search"] + tm["ms_substep"]) / 1e3 / K
+    b_interp, b_spread = ib_bytes(w, r32["touched"], 4)
+    avg_interp = tm["ms_interp"] / max(tm["n_interp"], 1)
+    avg_spread = tm["ms_spread"] / max(tm["n_spread"], 1)
+    kern = {"k_interp_mdf<float>": (b_interp, avg_interp),
+            "k_spread_mdf<float>": (b_spread, avg_spread)}
+    dom = max(kern, key=lambda k: kern[k][1])
+    bts, ms = kern[dom]
+    achieved = bts / (ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": w.n / t_step,
+        "unit": "particle-step/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n} equal spheres (D/h={w.d_over_h}, "
+                               f"{w.n_markers} markers each) in {w.domain[0]:g}x{w.domain[1]:g}x"
+                               f"{w.domain[2]:g} D, grid {w.grid[0]}x{w.grid[1]}x{w.grid[2]}",
+                   "spheres": w.n, "markers": M, "grid": list(w.grid),
+                   "forcing_iterations": iters, "substeps": W.PHYS["n_sub"],
+                   "precision": "grid and marker arithmetic f32, sphere state f64",
+                   "parallelism": "single GPU"},
+        "markers_per_s": M * iters / t_ib if t_ib > 0 else None,
+        "contacts_per_s": (r32["contacts"] / K) / t_dem if t_dem > 0 else None,
+        "phases_ms_per_step": {k[3:]: v / K for k, v in tm.items() if k.startswith("ms_")},
+        "touched_nodes": r32["touched"],
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": bts, "avg_launch_ms": ms,
+                     "interp": {"alg_bytes": b_interp, "avg_ms": avg_interp,
+                                "GBs": b_interp / avg_interp / 1e6},
+                     "spread": {"alg_bytes": b_spread, "avg_ms": avg_spread,
+                                "GBs": b_spread / avg_spread / 1e6}},
+    }
+    if not args.no_fp64:
+        K64 = max(1, min(K, 3))
+        r64 = run_form(P, W, w, bed, P.F64, K64, 1, torch)
+        t64 = r64["wall"] / K64
+        tm64 = r64["timing"]
+        out["fp64_plain"] = {
+            "value": w.n / t64, "unit": "particle-step/s", "ms_per_step": t64 * 1e3,
+            "steps": K64, "forcing_iterations": r64["stats"]["iterations"],
+            "phases_ms_per_step": {k[3:]: v / K64 for k, v in tm64.items() if k.startswith("ms_")},
+            "fp32_speedup": t64 / t_step,
+        }
+    if not args.no_cpu:
+        cb = cpu_baseline(W, w, bed)
+        cb.pop("rc", None)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,214 @@
+/*
+ * prs.h -- C ABI of the particle-phase step of the particle-resolved
+ * sediment-transport method of Zhu, Hu, Lei, Shen and Zheng (arXiv
+ * 2108.01814), built for AMD MI355X (gfx950).
+ *
+ * The step couples equal spheres to a fluid through a direct-forcing
+ * immersed boundary (interpolation and diffusion through a regularised delta
+ * function, sec. 3.3; forcing update eq. 4), resolves soft-sphere contacts
+ * (collision force and torque, eqs. 9-10 and Appendix A, with the
+ * fixed-capacity contact history of sec. 3.4) and advances the spheres by the
+ * Newton-Euler equations (eqs. 7-8).
+ *
+ * Conventions shared by every call:
+ *   - Units are those of the caller; the library never rescales.
+ *   - Every array argument is DEVICE memory owned by the caller, contiguous,
+ *     row-major, and is not retained after the call returns.  Host memory is
+ *     used only where an argument says so (prs_template, stats, counts).
+ *   - Particle vectors (positions x, velocities u, angular velocities omega,
+ *     forces, torques) are double [n][3].
+ *   - Grid fields use the staggered (MAC) layout of an nx*ny*nz box of
+ *     spacing h, periodic in x and z, walls at y = 0 and y = ny*h:
+ *       u: [nz][ny][nx]    at (i h, (j+1/2) h, (k+1/2) h)
+ *       v: [nz][ny+1][nx]  at ((i+1/2) h, j h, (k+1/2) h)
+ *       w: [nz][ny][nx]    at ((i+1/2) h, (j+1/2) h, k h)
+ *     x fastest; element type float (PRS_F32) or double (PRS_F64) as chosen
+ *     at prs_create.  Wall faces (v rows j = 0 and j = ny) never take part.
+ *   - Per-marker vectors are [n][n_markers][3] in the grid element type.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is queued on that stream; calls that return counts or statistics
+ *     synchronise with it before returning, as stated below.
+ *   - Every call validates its arguments on the host before launching any
+ *     work and returns a prs_status; prs_last_error() then describes it.
+ *     Device-side conditions (capacity, non-finite state, a sphere leaving
+ *     the domain) are reported through the status word at the next
+ *     synchronising return.
+ *   - One context per stream: a context's scratch memory is reused by every
+ *     call, so calls on one context must not overlap.
+ */
+#ifndef PRS_H
+#define PRS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum prs_status {
+    PRS_OK = 0,
+    PRS_EINVAL = 1,      /* invalid argument (detected on the host, nothing launched) */
+    PRS_ECAPACITY = 2,   /* a fixed capacity was exceeded (see the call) */
+    PRS_EDOMAIN = 3,     /* a sphere centre lies outside the box */
+    PRS_ENONFINITE = 4,  /* a NaN or infinity in the particle state */
+    PRS_EHIP = 5,        /* a HIP runtime call failed */
+    PRS_ESKIN = 6        /* a sphere moved farther than skin/2 within one step */
+} prs_status;
+
+enum { PRS_F32 = 0, PRS_F64 = 1 };
+
+#define PRS_SLOTS 14      /* contact slots per sphere: 12 spheres + 2 walls */
+#define PRS_MAX_PP 12     /* equal spheres touch at most twelve others (sec. 3.4) */
+#define PRS_WALL_BOTTOM (-1)
+#define PRS_WALL_TOP (-2)
+#define PRS_MAX_SLIP 64
+
+typedef struct prs_params {
+    /* Eulerian grid */
+    int32_t nx, ny, nz;
+    double h;
+    /* spheres (all of radius `radius`) and fluid */
+    double radius, rho_p, rho_f;
+    double gravity[3];
+    int32_t n_markers;   /* Lagrangian markers per sphere, 1 .. 1024 */
+    /* immersed boundary: the forcing update uses alpha*dt_f (eq. 4) */
+    double dt_f, alpha;
+    int32_t n_iter;      /* multi-direct-forcing iterations when tol_mode = 0 */
+    int32_t tol_mode;    /* 1: iterate until relative slip < tol or max_iter */
+    double tol;
+    int32_t max_iter;    /* <= PRS_MAX_SLIP - 1 */
+    /* contacts and particle substeps (dt_p = dt_f / n_sub) */
+    int32_t n_sub;
+    double k_n, e_n, mu, kt_ratio, dt_ratio;
+    double skin;         /* collision-search margin (>= 0), in length units */
+    int32_t precision;   /* PRS_F32 or PRS_F64 */
+    int32_t max_particles;
+} prs_params;
+
+typedef struct prs_ctx prs_ctx;
+
+/* Contact history M_p of sec. 3.4, caller-owned device memory, slots of
+ * sphere i at [i][0 .. cnt[i]-1]: partner index (another sphere, or
+ * PRS_WALL_BOTTOM / PRS_WALL_TOP), tangential displacement delta_t (A.9-A.11)
+ * and impact velocity u_in.  Slots are ordered by partner index ascending,
+ * then the bottom wall, then the top wall; unused slots read zero on output.
+ * An all-zero history means "no contacts yet". */
+typedef struct prs_history {
+    int32_t *partner;    /* [n][PRS_SLOTS] */
+    double *delta_t;     /* [n][PRS_SLOTS][3] */
+    double *u_in;        /* [n][PRS_SLOTS] */
+    int8_t *count;       /* [n] */
+} prs_history;
+
+typedef struct prs_stats {
+    int32_t iterations;                /* spreads performed (multi-direct forcing) */
+    int32_t n_slip;                    /* entries of rel_slip filled */
+    double rel_slip[PRS_MAX_SLIP];     /* ||U_d - I[u**]|| / ||U_d - I[u-hat]|| per interpolation */
+    int64_t contacts;                  /* directed contacts summed over all substeps */
+    int64_t pairs_last;                /* sphere-sphere pairs at the last substep */
+    int64_t wall_last;                 /* sphere-wall contacts at the last substep */
+    uint32_t flags;                    /* device status word (0 = clean) */
+    int32_t rejected_learned;          /* reserved: learned warm start rejected */
+} prs_stats;
+
+/* Create a context.  Checks the parameters, allocates the scratch memory for
+ * up to p->max_particles spheres on the current device and builds the marker
+ * template.  Returns PRS_EINVAL for inconsistent parameters (non-positive
+ * sizes, n_markers outside 1..1024, a periodic box shorter than three
+ * collision cells, ...), PRS_EHIP when allocation fails. */
+int prs_create(const prs_params *p, prs_ctx **out);
+void prs_destroy(prs_ctx *ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char *prs_last_error(const prs_ctx *ctx);
+
+/* Marker template (reading of sec. 3.5: one set of surface points shared by
+ * every sphere): unit vectors t_l of a Fibonacci sphere with its pole along
+ * y, and the marker volume dV = pi h (12 R^2 + h^2) / (3 n_markers).
+ * t_host: HOST array double [n_markers][3]; dV: HOST double.  Synchronous. */
+int prs_template(prs_ctx *ctx, double *t_host, double *dV);
+
+/* Interpolation (sec. 3.3): for every marker X = x_p + R t_l of every sphere,
+ * U_c = sum over the nodes of component c of g_c[node] * delta-kernel
+ * weights (regularised three-point kernel, periodic in x and z, wall rule
+ * above).  gu, gv, gw: grid fields; x, up, om: double [n][3];
+ * U: [n][n_markers][3] out; Ud: optional [n][n_markers][3] out, the rigid
+ * velocity u_p + omega_p x (R t_l) of each marker (NULL to skip).
+ * Asynchronous.  PRS_EINVAL for n > max_particles or missing arrays. */
+int prs_interpolate(prs_ctx *ctx, void *stream, const void *gu, const void *gv, const void *gw,
+                    const double *x, const double *up, const double *om, int32_t n, void *U,
+                    void *Ud);
+
+/* Diffusion / spreading (sec. 3.3), the adjoint of prs_interpolate:
+ * f_c[node] += F_c * weight * dV / h^3 for every marker.  F: [n][n_markers][3];
+ * fu, fv, fw: grid fields, accumulated into (accumulate != 0) or cleared
+ * first (accumulate == 0).  Accumulation uses atomic adds, so the summation
+ * order (and the last bits) may differ between runs.  Asynchronous. */
+int prs_spread(prs_ctx *ctx, void *stream, const double *x, int32_t n, const void *F, void *fu,
+               void *fv, void *fw, int accumulate);
+
+/* Contact detection (Appendix A, (A.3)-(A.4)): every sphere pair with
+ * minimum-image centre distance d, d^2 < (2R)^2, and every sphere with
+ * y < R (bottom wall) or ny*h - y < R (top wall).  pairs: device int32
+ * [cap][2] receiving rows (i, j), i < j for sphere pairs, j = PRS_WALL_BOTTOM
+ * or PRS_WALL_TOP for walls, ordered by i, then j ascending, then bottom wall,
+ * then top wall -- a canonical order independent of the device.  n_out: HOST
+ * int64, the number of contacts.  When it exceeds cap, only the first cap
+ * rows are written and PRS_ECAPACITY is returned; a sphere touching more
+ * than PRS_MAX_PP spheres also gives PRS_ECAPACITY.  Positions must satisfy
+ * 0 <= x < nx h, 0 <= y <= ny h, 0 <= z < nz h (else PRS_EDOMAIN /
+ * PRS_ENONFINITE).  Synchronous. */
+int prs_contacts(prs_ctx *ctx, void *stream, const double *x, int32_t n, int32_t *pairs,
+                 int64_t cap, int64_t *n_out);
+
+/* One particle-phase step (sec. 2.1 and 3): immersed-boundary forcing at the
+ * current sphere state, then n_sub contact + Newton-Euler substeps of
+ * dt_p = dt_f / n_sub with the hydrodynamic force and torque held fixed.
+ *
+ *   uhat  : 3 grid fields, the predicted fluid velocity u-hat (read only).
+ *   f     : 3 grid fields, in/out.  On entry the initial forcing field
+ *           (normally all zero; pass zero_f = 1 to have the call clear it);
+ *           on return the immersed-boundary force field.  The intermediate
+ *           velocity of eq. 4 is u-tilde = u-hat + alpha dt_f f; it is never
+ *           stored by the library.
+ *   x, u, om : double [n][3] sphere state, advanced in place.  Written only
+ *           at the very end and only when the step succeeded: on any error
+ *           they (and the history) keep their input values.
+ *   hist  : contact history, in/out (see prs_history).
+ *   Fh, Th: double [n][3] out, hydrodynamic force and torque on each sphere,
+ *           -rho_f dV sum_l F_l and -rho_f dV sum_l (R t_l) x F_l.
+ *   F0    : optional [n][n_markers][3] initial marker force (warm start),
+ *           spread before the first iteration; NULL for none.
+ *   stats : HOST, optional, filled on return.
+ * Synchronous on return.  Errors: PRS_EINVAL (arguments), PRS_ECAPACITY
+ * (more than PRS_MAX_PP touching spheres, or more than 32 collision-search
+ * candidates on one sphere), PRS_EDOMAIN, PRS_ENONFINITE, PRS_ESKIN (a sphere
+ * moved more than skin/2 during the substeps; retry with a larger skin). */
+int prs_step_particles(prs_ctx *ctx, void *stream, const void *const uhat[3], void *const f[3],
+                       int zero_f, double *x, double *u, double *om, int32_t n,
+                       const prs_history *hist, double *Fh, double *Th, const void *F0,
+                       prs_stats *stats);
+
+/* Per-phase device time of prs_step_particles, measured with HIP events
+ * recorded on the caller's stream around each phase (milliseconds summed
+ * over the steps since the last reset; launch counts alongside).  Phases:
+ * clearing f, sorting into cells (+ state gather), interpolation passes,
+ * spreading passes, the collision search, the particle substeps, the final
+ * write-back.  Timing costs two event records per phase; it is off unless
+ * enabled. */
+typedef struct prs_timing {
+    int64_t steps;
+    double ms_zero_f, ms_sort, ms_interp, ms_spread, ms_search, ms_substep, ms_writeback;
+    int64_t n_interp, n_spread, n_substep;
+} prs_timing;
+
+/* Enable (1) or disable (0) phase timing on this context. */
+int prs_timing_enable(prs_ctx *ctx, int enable);
+/* Copy the accumulated phase times into *out (HOST); reset them if reset != 0. */
+int prs_timing_read(prs_ctx *ctx, prs_timing *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRS_H */

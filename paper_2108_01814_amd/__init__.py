@@ -1,0 +1,317 @@
+"""Particle-phase step of the particle-resolved sediment-transport method
+(Zhu et al., arXiv 2108.01814) on AMD MI355X.
+
+Thin ctypes binding of ``libprs.so`` (declared in ``include/prs.h``): it only
+checks shapes, dtypes and devices of the torch tensors it is given and passes
+their device pointers and the current HIP stream to the library.  Every step
+of the computation runs in the library's HIP kernels; there is no fallback,
+and importing the binding without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprs.so")
+
+PRS_OK, PRS_EINVAL, PRS_ECAPACITY, PRS_EDOMAIN, PRS_ENONFINITE, PRS_EHIP, PRS_ESKIN = range(7)
+F32, F64 = 0, 1
+SLOTS = 14
+MAX_PP = 12
+WALL_BOTTOM, WALL_TOP = -1, -2
+MAX_SLIP = 64
+_NAMES = {1: "EINVAL", 2: "ECAPACITY", 3: "EDOMAIN", 4: "ENONFINITE", 5: "EHIP", 6: "ESKIN"}
+
+EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_interpolate",
+           "prs_spread", "prs_contacts", "prs_step_particles", "prs_timing_enable",
+           "prs_timing_read")
+
+
+class PrsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+        ("radius", C.c_double), ("rho_p", C.c_double), ("rho_f", C.c_double),
+        ("gravity", C.c_double * 3),
+        ("n_markers", C.c_int32),
+        ("dt_f", C.c_double), ("alpha", C.c_double),
+        ("n_iter", C.c_int32), ("tol_mode", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+        ("n_sub", C.c_int32),
+        ("k_n", C.c_double), ("e_n", C.c_double), ("mu", C.c_double), ("kt_ratio", C.c_double),
+        ("dt_ratio", C.c_double),
+        ("skin", C.c_double),
+        ("precision", C.c_int32),
+        ("max_particles", C.c_int32),
+    ]
+
+
+class _History(C.Structure):
+    _fields_ = [("partner", C.c_void_p), ("delta_t", C.c_void_p), ("u_in", C.c_void_p),
+                ("count", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int32), ("n_slip", C.c_int32),
+        ("rel_slip", C.c_double * MAX_SLIP),
+        ("contacts", C.c_int64), ("pairs_last", C.c_int64), ("wall_last", C.c_int64),
+        ("flags", C.c_uint32), ("rejected_learned", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(iterations=self.iterations, rel_slip=list(self.rel_slip[: self.n_slip]),
+                    contacts=self.contacts, pairs_last=self.pairs_last,
+                    wall_last=self.wall_last, flags=self.flags)
+
+
+class Timing(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("ms_zero_f", C.c_double), ("ms_sort", C.c_double),
+                ("ms_interp", C.c_double), ("ms_spread", C.c_double), ("ms_search", C.c_double),
+                ("ms_substep", C.c_double), ("ms_writeback", C.c_double),
+                ("n_interp", C.c_int64), ("n_spread", C.c_int64), ("n_substep", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libprs.so; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2108_01814_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.prs_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.prs_destroy.argtypes = [vp]
+        L.prs_destroy.restype = None
+        L.prs_last_error.argtypes = [vp]
+        L.prs_last_error.restype = C.c_char_p
+        L.prs_template.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.prs_interpolate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
+        L.prs_spread.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int]
+        L.prs_contacts.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.prs_step_particles.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), C.c_int, vp, vp,
+                                         vp, C.c_int32, C.POINTER(_History), vp, vp, vp,
+                                         C.POINTER(Stats)]
+        L.prs_timing_enable.argtypes = [vp, C.c_int]
+        L.prs_timing_read.argtypes = [vp, C.POINTER(Timing), C.c_int]
+        _lib = L
+    return _lib
+
+
+def make_params(**kw) -> Params:
+    p = Params()
+    d = dict(h=0.1, radius=0.5, rho_p=2.65, rho_f=1.0, gravity=(0.0, -1.0, 0.0), n_markers=314,
+             dt_f=8.27944e-4, alpha=1.0, n_iter=3, tol_mode=0, tol=1e-6, max_iter=10, n_sub=20,
+             k_n=1e5, e_n=0.9, mu=0.5, kt_ratio=2.0 / 7.0, dt_ratio=2.0 / 7.0, skin=0.1,
+             precision=F64, max_particles=1)
+    d.update(kw)
+    for k, v in d.items():
+        if k == "gravity":
+            p.gravity = (C.c_double * 3)(*v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _stream_ptr():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+@dataclass
+class History:
+    """Contact history M_p (sec. 3.4) as device tensors."""
+    partner: "object"
+    delta_t: "object"
+    u_in: "object"
+    count: "object"
+
+    @classmethod
+    def zeros(cls, n: int, device="cuda"):
+        import torch
+
+        return cls(torch.zeros((n, SLOTS), dtype=torch.int32, device=device),
+                   torch.zeros((n, SLOTS, 3), dtype=torch.float64, device=device),
+                   torch.zeros((n, SLOTS), dtype=torch.float64, device=device),
+                   torch.zeros((n,), dtype=torch.int8, device=device))
+
+    def clone(self):
+        return History(self.partner.clone(), self.delta_t.clone(), self.u_in.clone(),
+                       self.count.clone())
+
+    def _c(self):
+        return _History(self.partner.data_ptr(), self.delta_t.data_ptr(), self.u_in.data_ptr(),
+                        self.count.data_ptr())
+
+
+class Context:
+    """One library context (scratch for up to max_particles spheres)."""
+
+    def __init__(self, params: Params):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the particle step needs a ROCm GPU")
+        self.p = params
+        self._h = C.c_void_p()
+        rc = lib().prs_create(C.byref(params), C.byref(self._h))
+        if rc != PRS_OK:
+            raise PrsError(rc, "prs_create rejected the parameters or could not allocate")
+        self.dtype = torch.float64 if params.precision == F64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if self._h:
+            lib().prs_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def timing(self, enable: bool = True):
+        """Switch per-phase event timing of step() on or off."""
+        self._err(lib().prs_timing_enable(self._h, int(bool(enable))))
+
+    def read_timing(self, reset: bool = True) -> dict:
+        t = Timing()
+        self._err(lib().prs_timing_read(self._h, C.byref(t), int(bool(reset))))
+        return t.as_dict()
+
+    # -- argument checks (the library cannot see tensor sizes) --------------
+    def _err(self, rc):
+        if rc != PRS_OK:
+            raise PrsError(rc, lib().prs_last_error(self._h).decode())
+
+    def _chk(self, t, shape, dtype, name):
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name}: dtype {t.dtype} != {dtype}")
+        if t.device != self.device:
+            raise ValueError(f"{name}: on {t.device}, expected {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def grid_shapes(self):
+        p = self.p
+        return ((p.nz, p.ny, p.nx), (p.nz, p.ny + 1, p.nx), (p.nz, p.ny, p.nx))
+
+    def _chk_fields(self, fields: Sequence, name):
+        if len(fields) != 3:
+            raise ValueError(f"{name}: three components expected")
+        for c, (t, s) in enumerate(zip(fields, self.grid_shapes())):
+            self._chk(t, s, self.dtype, f"{name}[{c}]")
+
+    def _chk_particles(self, n, **arrays):
+        import torch
+
+        for k, t in arrays.items():
+            self._chk(t, (n, 3), torch.float64, k)
+
+    # -- calls ---------------------------------------------------------------
+    def template(self):
+        import numpy as np
+
+        t = np.zeros((self.p.n_markers, 3))
+        dV = C.c_double()
+        self._err(lib().prs_template(self._h, C.c_void_p(t.ctypes.data), C.byref(dV)))
+        return t, dV.value
+
+    def interpolate(self, fields, x, up=None, om=None, want_ud=False):
+        import torch
+
+        n = x.shape[0]
+        self._chk_fields(fields, "fields")
+        self._chk_particles(n, x=x)
+        if want_ud:
+            self._chk_particles(n, up=up, om=om)
+        U = torch.empty((n, self.p.n_markers, 3), dtype=self.dtype, device=self.device)
+        Ud = torch.empty_like(U) if want_ud else None
+        self._err(lib().prs_interpolate(self._h, _stream_ptr(), _ptr(fields[0]), _ptr(fields[1]),
+                                        _ptr(fields[2]), _ptr(x), _ptr(up if want_ud else None),
+                                        _ptr(om if want_ud else None), n, _ptr(U), _ptr(Ud)))
+        return (U, Ud) if want_ud else U
+
+    def spread(self, x, F, fields, accumulate=True):
+        n = x.shape[0]
+        self._chk_particles(n, x=x)
+        self._chk(F, (n, self.p.n_markers, 3), self.dtype, "F")
+        self._chk_fields(fields, "fields")
+        self._err(lib().prs_spread(self._h, _stream_ptr(), _ptr(x), n, _ptr(F), _ptr(fields[0]),
+                                   _ptr(fields[1]), _ptr(fields[2]), int(bool(accumulate))))
+
+    def contacts(self, x, cap: Optional[int] = None):
+        """Canonical contact list as an int32 [n_contacts, 2] device tensor."""
+        import torch
+
+        n = x.shape[0]
+        self._chk_particles(n, x=x)
+        if cap is None:
+            cap = 8 * max(n, 1)
+        pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
+        n_out = C.c_int64()
+        rc = lib().prs_contacts(self._h, _stream_ptr(), _ptr(x), n, _ptr(pairs), cap,
+                                C.byref(n_out))
+        if rc == PRS_ECAPACITY and n_out.value > cap:
+            return self.contacts(x, cap=int(n_out.value))
+        self._err(rc)
+        return pairs[: n_out.value]
+
+    def step(self, uhat, f, x, u, om, hist: History, Fh=None, Th=None, F0=None, zero_f=False):
+        """One particle step in place (x, u, om, hist, f); returns (Fh, Th, stats)."""
+        import torch
+
+        n = x.shape[0]
+        self._chk_fields(uhat, "uhat")
+        self._chk_fields(f, "f")
+        self._chk_particles(n, x=x, u=u, om=om)
+        self._chk(hist.partner, (n, SLOTS), torch.int32, "hist.partner")
+        self._chk(hist.delta_t, (n, SLOTS, 3), torch.float64, "hist.delta_t")
+        self._chk(hist.u_in, (n, SLOTS), torch.float64, "hist.u_in")
+        self._chk(hist.count, (n,), torch.int8, "hist.count")
+        if Fh is None:
+            Fh = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if Th is None:
+            Th = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        self._chk_particles(n, Fh=Fh, Th=Th)
+        if F0 is not None:
+            self._chk(F0, (n, self.p.n_markers, 3), self.dtype, "F0")
+        uh = (C.c_void_p * 3)(*[t.data_ptr() for t in uhat])
+        ff = (C.c_void_p * 3)(*[t.data_ptr() for t in f])
+        H = hist._c()
+        st = Stats()
+        rc = lib().prs_step_particles(self._h, _stream_ptr(), uh, ff, int(bool(zero_f)), _ptr(x),
+                                      _ptr(u), _ptr(om), n, C.byref(H), _ptr(Fh), _ptr(Th),
+                                      _ptr(F0), C.byref(st))
+        self._err(rc)
+        return Fh, Th, st.as_dict()

@@ -1,0 +1,547 @@
+// extern "C" boundary of the library: argument validation, context and
+// scratch management, and the host-side sequencing of the kernels on the
+// caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "prs_internal.h"
+
+using namespace prs;
+
+struct prs_ctx {
+  prs_params p{};
+  Geom G{};
+  Cells C_step{}, C_touch{};
+  Mech M{};
+  Scratch S{};
+  int device = 0;
+  std::vector<void *> allocs;
+  std::string err;
+  double *host_pinned = nullptr;   // staging for statistics
+  // phase timing (prs_timing_*)
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t events_used = 0;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  hipEvent_t open_ev = nullptr;
+  double ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t launches[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t steps = 0;
+};
+
+namespace {
+
+int fail(prs_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((ctx), PRS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+template <typename T>
+int alloc(prs_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  const size_t bytes = (count ? count : 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess)
+    return fail(c, PRS_EHIP, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return PRS_OK;
+}
+
+// Cells of edge >= cut (with a relative margin so that rounding never puts
+// two spheres closer than cut into non-adjacent cells).
+Cells make_cells(const Geom &G, double cut) {
+  Cells C{};
+  const double c = cut * (1.0 + 1e-9);
+  C.ncx = (int)std::floor(G.Lx / c);
+  C.ncy = (int)std::floor(G.Ly / c);
+  C.ncz = (int)std::floor(G.Lz / c);
+  if (C.ncy < 1) C.ncy = 1;
+  C.csx = G.Lx / (C.ncx > 0 ? C.ncx : 1);
+  C.csy = G.Ly / C.ncy;
+  C.csz = G.Lz / (C.ncz > 0 ? C.ncz : 1);
+  C.ntx = (C.ncx + 3) / 4;
+  C.nty = (C.ncy + 3) / 4;
+  C.ntz = (C.ncz + 3) / 4;
+  C.nkeys = C.ntx * C.nty * C.ntz * 64;
+  return C;
+}
+
+double damping(double k, double e, double m_eff) {
+  const double le = std::log(e);
+  return -2.0 * le * std::sqrt(m_eff * k) / std::sqrt(M_PI * M_PI + le * le);
+}
+
+size_t grid_count(const prs_ctx *c, int comp) {
+  return (size_t)c->p.nz * (size_t)(c->p.ny + (comp == 1 ? 1 : 0)) * (size_t)c->p.nx;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+int status_code(uint32_t st) {
+  if (st & kFlagNonFinite) return PRS_ENONFINITE;
+  if (st & kFlagDomain) return PRS_EDOMAIN;
+  if (st & (kFlagSlots | kFlagCand)) return PRS_ECAPACITY;
+  if (st & kFlagSkin) return PRS_ESKIN;
+  return PRS_OK;
+}
+
+const char *status_text(uint32_t st) {
+  if (st & kFlagNonFinite) return "non-finite value in the sphere state";
+  if (st & kFlagDomain) return "a sphere centre lies outside the box";
+  if (st & kFlagSlots) return "a sphere touches more than twelve spheres";
+  if (st & kFlagCand) return "more than 32 collision-search candidates on one sphere";
+  if (st & kFlagSkin) return "a sphere moved farther than skin/2 within the step";
+  return "ok";
+}
+
+int check_n(prs_ctx *c, int32_t n) {
+  if (n < 0 || n > c->p.max_particles)
+    return fail(c, PRS_EINVAL, "n = %d outside 0..max_particles (%d)", n, c->p.max_particles);
+  return PRS_OK;
+}
+
+enum Phase { kZeroF = 0, kSort, kInterp, kSpread, kSearch, kSubstep, kWriteback };
+
+hipError_t next_event(prs_ctx *c, hipEvent_t *ev) {
+  if (c->events_used == c->events.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->events.push_back(e);
+  }
+  *ev = c->events[c->events_used++];
+  return hipSuccess;
+}
+
+hipError_t phase_begin(prs_ctx *c, hipStream_t s) {
+  if (!c->timing) return hipSuccess;
+  hipError_t r = next_event(c, &c->open_ev);
+  return r != hipSuccess ? r : hipEventRecord(c->open_ev, s);
+}
+
+hipError_t phase_end(prs_ctx *c, hipStream_t s, int phase) {
+  if (!c->timing) return hipSuccess;
+  hipEvent_t e;
+  hipError_t r = next_event(c, &e);
+  if (r != hipSuccess) return r;
+  r = hipEventRecord(e, s);
+  c->marks.push_back({phase, c->open_ev, e});
+  return r;
+}
+
+// After the stream has been synchronised: fold the recorded intervals in.
+hipError_t phase_collect(prs_ctx *c) {
+  if (!c->timing) return hipSuccess;
+  for (const auto &m : c->marks) {
+    float ms = 0.f;
+    hipError_t r = hipEventElapsedTime(&ms, m.a, m.b);
+    if (r != hipSuccess) return r;
+    c->ms[m.phase] += ms;
+    c->launches[m.phase] += 1;
+  }
+  c->marks.clear();
+  c->events_used = 0;
+  c->steps += 1;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prs_create(const prs_params *p, prs_ctx **out) {
+  if (!p || !out) return PRS_EINVAL;
+  *out = nullptr;
+  const prs_params &q = *p;
+  auto bad = [&](const char *what) {
+    (void)what;
+    return PRS_EINVAL;
+  };
+  if (q.nx < 1 || q.ny < 1 || q.nz < 1 || !(q.h > 0) || !(q.radius > 0)) return bad("grid");
+  if (q.n_markers < 1 || q.n_markers > kMaxMarkers) return bad("n_markers");
+  if (!(q.rho_p > 0) || !(q.rho_f >= 0) || !(q.dt_f > 0) || !(q.alpha > 0)) return bad("phys");
+  if (q.n_iter < 0 || q.max_iter < 0 || q.max_iter > PRS_MAX_SLIP - 1 ||
+      q.n_iter > PRS_MAX_SLIP - 1)
+    return bad("iter");
+  if (q.tol_mode != 0 && q.tol_mode != 1) return bad("tol_mode");
+  if (q.n_sub < 0 || !(q.k_n > 0) || !(q.e_n > 0 && q.e_n <= 1) || !(q.mu >= 0) ||
+      !(q.kt_ratio > 0) || !(q.dt_ratio >= 0) || !(q.skin >= 0))
+    return bad("contact");
+  if (q.precision != PRS_F32 && q.precision != PRS_F64) return bad("precision");
+  if (q.max_particles < 0) return bad("max_particles");
+  for (double gv : q.gravity)
+    if (!std::isfinite(gv)) return bad("gravity");
+
+  prs_ctx *c = new prs_ctx();
+  c->p = q;
+  Geom &G = c->G;
+  G.nx = q.nx;
+  G.ny = q.ny;
+  G.nz = q.nz;
+  G.h = q.h;
+  G.inv_h = 1.0 / q.h;
+  G.Lx = q.nx * q.h;
+  G.Ly = q.ny * q.h;
+  G.Lz = q.nz * q.h;
+  G.R = q.radius;
+  G.nl = q.n_markers;
+  G.dV = M_PI * q.h * (12.0 * q.radius * q.radius + q.h * q.h) / (3.0 * q.n_markers);
+  // the stencil of a marker must not wrap twice around the periodic box
+  if (!(G.Lx > q.radius + 3 * q.h) || !(G.Lz > q.radius + 3 * q.h)) {
+    delete c;
+    return PRS_EINVAL;
+  }
+  c->C_step = make_cells(G, 2.0 * q.radius + q.skin);
+  c->C_touch = make_cells(G, 2.0 * q.radius);
+  if (c->C_step.ncx < 3 || c->C_step.ncz < 3) {
+    delete c;
+    return PRS_EINVAL;
+  }
+  // every argument check above runs before the first HIP call
+  (void)hipGetDevice(&c->device);
+  Mech &M = c->M;
+  const double R = q.radius;
+  M.m = q.rho_p * (4.0 / 3.0) * M_PI * R * R * R;
+  M.I = 0.4 * M.m * R * R;
+  const double V = (4.0 / 3.0) * M_PI * R * R * R;
+  for (int a = 0; a < 3; ++a) M.fg[a] = (q.rho_p - q.rho_f) * V * q.gravity[a];
+  M.kn = q.k_n;
+  M.dn_pp = damping(q.k_n, q.e_n, 0.5 * M.m);
+  M.dn_pw = damping(q.k_n, q.e_n, M.m);
+  M.kt = q.kt_ratio * q.k_n;
+  M.dt_pp = q.dt_ratio * M.dn_pp;
+  M.dt_pw = q.dt_ratio * M.dn_pw;
+  M.mu = q.mu;
+  M.dtp = q.n_sub > 0 ? q.dt_f / q.n_sub : 0.0;
+  M.skin_half2 = 0.25 * q.skin * q.skin;
+
+  Scratch &S = c->S;
+  const size_t n = (size_t)(q.max_particles > 0 ? q.max_particles : 1);
+  const int nkeys = c->C_step.nkeys > c->C_touch.nkeys ? c->C_step.nkeys : c->C_touch.nkeys;
+  const size_t scan_max = (size_t)(nkeys > (int)n ? nkeys : (int)n) + 1;
+  S.cap_n = (int)n;
+  S.scan_tmp_elems = scan_max / 1024 + 64;
+  const size_t esz = q.precision == PRS_F64 ? 8 : 4;
+  int rc = PRS_OK;
+  rc |= alloc(c, &S.key, n);
+  rc |= alloc(c, &S.start, (size_t)nkeys + 1);
+  rc |= alloc(c, &S.fill, (size_t)nkeys);
+  rc |= alloc(c, &S.perm, n);
+  rc |= alloc(c, &S.inv_perm, n);
+  rc |= alloc(c, &S.scan_tmp, S.scan_tmp_elems);
+  for (int b = 0; b < 2; ++b) {
+    rc |= alloc(c, &S.xs[b], 3 * n);
+    rc |= alloc(c, &S.us[b], 3 * n);
+    rc |= alloc(c, &S.ws[b], 3 * n);
+    rc |= alloc(c, &S.h_cnt[b], n);
+    rc |= alloc(c, &S.h_id[b], kSlots * n);
+    rc |= alloc(c, &S.h_dt[b], 3 * kSlots * n);
+    rc |= alloc(c, &S.h_uin[b], kSlots * n);
+  }
+  rc |= alloc(c, &S.x0, 3 * n);
+  rc |= alloc(c, &S.fh, 3 * n);
+  rc |= alloc(c, &S.th, 3 * n);
+  rc |= alloc(c, &S.ft_acc, 12 * n);
+  rc |= alloc(c, &S.slip_part, 2 * n);
+  rc |= alloc(c, &S.slip_hist, 2 * PRS_MAX_SLIP);
+  rc |= alloc(c, &S.ncand, n);
+  rc |= alloc(c, &S.cand, (size_t)kCandCap * n);
+  rc |= alloc(c, &S.ccount, n + 1);
+  S.coffset = S.ccount;
+  char *dF = nullptr;
+  rc |= alloc(c, &dF, 3 * n * (size_t)q.n_markers * esz);
+  S.dF = dF;
+  rc |= alloc(c, &S.status, 4);
+  rc |= alloc(c, &S.counters, 4);
+  rc |= alloc(c, &S.templ, 3 * (size_t)q.n_markers);
+  if (rc != PRS_OK) {
+    prs_destroy(c);
+    return PRS_EHIP;
+  }
+  if (hipHostMalloc((void **)&c->host_pinned, 256 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    prs_destroy(c);
+    return PRS_EHIP;
+  }
+  if (launch_template(nullptr, S.templ, q.n_markers) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    prs_destroy(c);
+    return PRS_EHIP;
+  }
+  *out = c;
+  return PRS_OK;
+}
+
+void prs_destroy(prs_ctx *c) {
+  if (!c) return;
+  for (void *q : c->allocs) (void)hipFree(q);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+  delete c;
+}
+
+const char *prs_last_error(const prs_ctx *c) {
+  if (!c) return "null context";
+  return c->err.empty() ? "ok" : c->err.c_str();
+}
+
+int prs_template(prs_ctx *c, double *t_host, double *dV) {
+  if (!c) return PRS_EINVAL;
+  if (!t_host || !dV) return fail(c, PRS_EINVAL, "template: null output");
+  HIP_TRY(c, hipMemcpy(t_host, c->S.templ, sizeof(double) * 3 * c->p.n_markers,
+                       hipMemcpyDeviceToHost));
+  *dV = c->G.dV;
+  return PRS_OK;
+}
+
+int prs_interpolate(prs_ctx *c, void *stream, const void *gu, const void *gv, const void *gw,
+                    const double *x, const double *up, const double *om, int32_t n, void *U,
+                    void *Ud) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (n == 0) return PRS_OK;
+  if (!gu || !gv || !gw || !x || !U) return fail(c, PRS_EINVAL, "interpolate: null array");
+  if (Ud && (!up || !om))
+    return fail(c, PRS_EINVAL, "interpolate: Ud needs up and om");
+  hipStream_t s = as_stream(stream);
+  if (c->p.precision == PRS_F64)
+    HIP_TRY(c, launch_interp_plain<double>(s, c->G, c->S.templ, (const double *)gu,
+                                           (const double *)gv, (const double *)gw, x, up, om, n,
+                                           (double *)U, (double *)Ud));
+  else
+    HIP_TRY(c, launch_interp_plain<float>(s, c->G, c->S.templ, (const float *)gu,
+                                          (const float *)gv, (const float *)gw, x, up, om, n,
+                                          (float *)U, (float *)Ud));
+  return PRS_OK;
+}
+
+int prs_spread(prs_ctx *c, void *stream, const double *x, int32_t n, const void *F, void *fu,
+               void *fv, void *fw, int accumulate) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!fu || !fv || !fw) return fail(c, PRS_EINVAL, "spread: null field");
+  if (n > 0 && (!x || !F)) return fail(c, PRS_EINVAL, "spread: null array");
+  hipStream_t s = as_stream(stream);
+  void *g[3] = {fu, fv, fw};
+  if (c->p.precision == PRS_F64) {
+    if (!accumulate)
+      for (int k = 0; k < 3; ++k)
+        HIP_TRY(c, launch_fill_zero<double>(s, (double *)g[k], grid_count(c, k)));
+    HIP_TRY(c, launch_spread_plain<double>(s, c->G, c->S.templ, x, n, (const double *)F,
+                                           (double *)fu, (double *)fv, (double *)fw));
+  } else {
+    if (!accumulate)
+      for (int k = 0; k < 3; ++k)
+        HIP_TRY(c, launch_fill_zero<float>(s, (float *)g[k], grid_count(c, k)));
+    HIP_TRY(c, launch_spread_plain<float>(s, c->G, c->S.templ, x, n, (const float *)F,
+                                          (float *)fu, (float *)fv, (float *)fw));
+  }
+  return PRS_OK;
+}
+
+int prs_contacts(prs_ctx *c, void *stream, const double *x, int32_t n, int32_t *pairs,
+                 int64_t cap, int64_t *n_out) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!n_out) return fail(c, PRS_EINVAL, "contacts: null n_out");
+  if (cap < 0 || (cap > 0 && !pairs)) return fail(c, PRS_EINVAL, "contacts: bad pairs/cap");
+  if (n > 0 && !x) return fail(c, PRS_EINVAL, "contacts: null positions");
+  *n_out = 0;
+  hipStream_t s = as_stream(stream);
+  Scratch &S = c->S;
+  HIP_TRY(c, launch_reset_status(s, S));
+  HIP_TRY(c, launch_sort(s, S, c->C_touch, c->G, x, n, 0));
+  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n));
+  HIP_TRY(c, launch_contact_list(s, S, c->C_touch, c->G, n, pairs, cap, 0));
+  if (n > 0) HIP_TRY(c, launch_scan(s, S.ccount, n, S.scan_tmp));
+  HIP_TRY(c, launch_contact_list(s, S, c->C_touch, c->G, n, pairs, cap, 1));
+  int total = 0;
+  uint32_t st = 0;
+  if (n > 0)
+    HIP_TRY(c, hipMemcpyAsync(&total, S.ccount + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(&st, S.status, sizeof st, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (int code = status_code(st)) return fail(c, code, "contacts: %s", status_text(st));
+  *n_out = total;
+  if (total > cap)
+    return fail(c, PRS_ECAPACITY, "contacts: %d contacts exceed cap %lld", total, (long long)cap);
+  return PRS_OK;
+}
+
+int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void *const f[3],
+                       int zero_f, double *x, double *u, double *om, int32_t n,
+                       const prs_history *H, double *Fh, double *Th, const void *F0,
+                       prs_stats *stats) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!uhat || !f || !uhat[0] || !uhat[1] || !uhat[2] || !f[0] || !f[1] || !f[2])
+    return fail(c, PRS_EINVAL, "step: null field");
+  if (n > 0 && (!x || !u || !om || !Fh || !Th || !H || !H->partner || !H->delta_t || !H->u_in ||
+                !H->count))
+    return fail(c, PRS_EINVAL, "step: null particle array");
+  hipStream_t s = as_stream(stream);
+  Scratch &S = c->S;
+  const prs_params &q = c->p;
+  const double adt = q.alpha * q.dt_f;
+  const bool f64 = q.precision == PRS_F64;
+
+  HIP_TRY(c, launch_reset_status(s, S));
+  c->marks.clear();
+  c->events_used = 0;
+  if (zero_f) {
+    HIP_TRY(c, phase_begin(c, s));
+    for (int k = 0; k < 3; ++k) {
+      if (f64)
+        HIP_TRY(c, launch_fill_zero<double>(s, (double *)f[k], grid_count(c, k)));
+      else
+        HIP_TRY(c, launch_fill_zero<float>(s, (float *)f[k], grid_count(c, k)));
+    }
+    HIP_TRY(c, phase_end(c, s, kZeroF));
+  }
+  if (n > 0) {
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_sort(s, S, c->C_step, c->G, x, n, 0));
+    HIP_TRY(c, launch_gather_state(s, S, c->G, x, u, om, H, n));
+    HIP_TRY(c, phase_end(c, s, kSort));
+  }
+
+  // ---- immersed-boundary forcing (multi-direct forcing, Jacobi) ----
+  int iters = 0, n_slip = 0;
+  double *hist_host = c->host_pinned;   // [0..63] slip^2, [64] zero-forcing slip^2
+  if (n > 0) {
+    if (F0) {
+      HIP_TRY(c, phase_begin(c, s));
+      if (f64)
+        HIP_TRY(c, launch_spread_mdf<double>(s, c->G, S, (double **)f, n, (const double *)F0));
+      else
+        HIP_TRY(c, launch_spread_mdf<float>(s, c->G, S, (float **)f, n, (const float *)F0));
+      HIP_TRY(c, phase_end(c, s, kSpread));
+    } else {
+      HIP_TRY(c, launch_ib_begin(s, S, n));
+    }
+    const int limit = q.tol_mode ? q.max_iter : q.n_iter;
+    for (int it = 0;; ++it) {
+      if (!q.tol_mode && it >= q.n_iter) break;
+      HIP_TRY(c, phase_begin(c, s));
+      if (f64)
+        HIP_TRY(c, launch_interp_mdf<double>(s, c->G, S, (const double **)uhat,
+                                             (const double **)f, n, adt, it, it == 0));
+      else
+        HIP_TRY(c, launch_interp_mdf<float>(s, c->G, S, (const float **)uhat, (const float **)f,
+                                            n, adt, it, it == 0));
+      HIP_TRY(c, phase_end(c, s, kInterp));
+      HIP_TRY(c, launch_slip_reduce(s, S, n, it, it == 0));
+      n_slip = it + 1;
+      if (q.tol_mode) {
+        HIP_TRY(c, hipMemcpyAsync(hist_host + it, S.slip_hist + it, sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+        if (it == 0)
+          HIP_TRY(c, hipMemcpyAsync(hist_host + PRS_MAX_SLIP, S.slip_hist + PRS_MAX_SLIP,
+                                    sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
+        const double rel = den > 0 ? std::sqrt(hist_host[it]) / den : 0.0;
+        if (rel < q.tol || it >= limit) break;
+      }
+      HIP_TRY(c, phase_begin(c, s));
+      if (f64)
+        HIP_TRY(c, launch_spread_mdf<double>(s, c->G, S, (double **)f, n, nullptr));
+      else
+        HIP_TRY(c, launch_spread_mdf<float>(s, c->G, S, (float **)f, n, nullptr));
+      HIP_TRY(c, phase_end(c, s, kSpread));
+      iters = it + 1;
+    }
+    HIP_TRY(c, launch_ib_finish(s, S, c->G, n, q.rho_f));
+
+    // ---- contacts and Newton-Euler substeps ----
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_candidates(s, S, c->C_step, c->G, n, 2.0 * q.radius + q.skin));
+    HIP_TRY(c, phase_end(c, s, kSearch));
+    for (int sub = 0; sub < q.n_sub; ++sub) {
+      HIP_TRY(c, phase_begin(c, s));
+      HIP_TRY(c, launch_substep(s, S, c->G, c->M, n, sub & 1, sub == q.n_sub - 1));
+      HIP_TRY(c, phase_end(c, s, kSubstep));
+    }
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_writeback(s, S, x, u, om, H, Fh, Th, n, q.n_sub & 1));
+    HIP_TRY(c, phase_end(c, s, kWriteback));
+  }
+
+  uint32_t st = 0;
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpyAsync(&st, S.status, sizeof st, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(cnt, S.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
+  if (n_slip > 0)
+    HIP_TRY(c, hipMemcpyAsync(hist_host, S.slip_hist, sizeof(double) * (PRS_MAX_SLIP + 1),
+                              hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, phase_collect(c));
+  if (stats) {
+    memset(stats, 0, sizeof *stats);
+    stats->iterations = iters;
+    stats->n_slip = n_slip;
+    const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
+    for (int k = 0; k < n_slip; ++k)
+      stats->rel_slip[k] = den > 0 ? std::sqrt(hist_host[k]) / den : 0.0;
+    stats->contacts = (int64_t)cnt[0];
+    stats->pairs_last = (int64_t)cnt[1] / 2;
+    stats->wall_last = (int64_t)cnt[2];
+    stats->flags = st;
+  }
+  if (int code = status_code(st)) return fail(c, code, "step: %s", status_text(st));
+  return PRS_OK;
+}
+
+int prs_timing_enable(prs_ctx *c, int enable) {
+  if (!c) return PRS_EINVAL;
+  c->timing = enable != 0;
+  c->marks.clear();
+  c->events_used = 0;
+  return PRS_OK;
+}
+
+int prs_timing_read(prs_ctx *c, prs_timing *out, int reset) {
+  if (!c || !out) return PRS_EINVAL;
+  out->steps = c->steps;
+  out->ms_zero_f = c->ms[kZeroF];
+  out->ms_sort = c->ms[kSort];
+  out->ms_interp = c->ms[kInterp];
+  out->ms_spread = c->ms[kSpread];
+  out->ms_search = c->ms[kSearch];
+  out->ms_substep = c->ms[kSubstep];
+  out->ms_writeback = c->ms[kWriteback];
+  out->n_interp = c->launches[kInterp];
+  out->n_spread = c->launches[kSpread];
+  out->n_substep = c->launches[kSubstep];
+  if (reset) {
+    for (int k = 0; k < 7; ++k) {
+      c->ms[k] = 0.0;
+      c->launches[k] = 0;
+    }
+    c->steps = 0;
+  }
+  return PRS_OK;
+}
+
+}  // extern "C"

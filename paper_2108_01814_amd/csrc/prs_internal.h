@@ -1,0 +1,123 @@
+// Internal declarations of the HIP implementation behind include/prs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "prs.h"
+
+namespace prs {
+
+constexpr int kSlots = PRS_SLOTS;
+constexpr int kMaxPP = PRS_MAX_PP;
+constexpr int kCandCap = 32;   // collision-search candidates per sphere
+constexpr int kMaxMarkers = 1024;
+
+// Device status word bits.
+enum : uint32_t {
+  kFlagSlots = 1u << 0,      // a sphere touches more than twelve spheres
+  kFlagCand = 1u << 1,       // more than kCandCap search candidates
+  kFlagNonFinite = 1u << 2,  // NaN / inf in the sphere state
+  kFlagDomain = 1u << 3,     // a centre outside the box
+  kFlagSkin = 1u << 4,       // displacement beyond skin/2 within a step
+};
+
+// Box, grid and sphere geometry as seen by the kernels.
+struct Geom {
+  int nx, ny, nz;
+  double h, inv_h;
+  double Lx, Ly, Lz;
+  double R;
+  int nl;
+  double dV;
+};
+
+// Collision cells: an ncx*ncy*ncz partition of the box, cell edges >= the
+// search cut-off; cells are numbered by 4x4x4 tiles (tile-major, Morton order
+// inside a tile) so that spheres sorted by cell number are close in space.
+struct Cells {
+  int ncx, ncy, ncz;
+  double csx, csy, csz;
+  int ntx, nty, ntz;
+  int nkeys;
+};
+
+// Sphere mechanics.
+struct Mech {
+  double m, I;
+  double fg[3];           // buoyant weight (rho_p - rho_f) V g
+  double kn, dn_pp, dn_pw, kt, dt_pp, dt_pw, mu;
+  double dtp;             // particle substep
+  double skin_half2;      // (skin/2)^2
+};
+
+// Scratch owned by a context.
+struct Scratch {
+  int cap_n;
+  // sorting / cell list
+  int *key, *count, *fill, *start, *perm, *inv_perm;
+  int *scan_tmp;
+  size_t scan_tmp_elems;
+  // sorted sphere state, double-buffered SoA [3][n]
+  double *xs[2], *us[2], *ws[2], *x0;
+  double *fh, *th;            // [3][n] sorted
+  double *ft_acc;             // [12][n]: (sum, compensation) x (Fx Fy Fz Tx Ty Tz)
+  double *slip_part;          // [2][n]: slip^2 and zero-forcing slip^2 per sphere
+  double *slip_hist;          // [2][kMaxSlip]
+  int *ncand, *cand;          // [n], [kCandCap][n]
+  // contact history, internal SoA layout [slot][n], double-buffered
+  int *h_cnt[2], *h_id[2];
+  double *h_dt[2], *h_uin[2];
+  // contact listing
+  int *ccount, *coffset;
+  // marker corrections dF [3][n*nl] in grid precision
+  void *dF;
+  // status and counters
+  uint32_t *status;
+  unsigned long long *counters;   // [0] directed contacts, [1] pp last, [2] wall last
+  double *templ;                  // [nl][3]
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_template(hipStream_t s, double *t, int nl);
+
+hipError_t launch_sort(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
+                       const double *x_caller, int n, int nkeys_scan_levels);
+hipError_t launch_gather_state(hipStream_t s, const Scratch &S, const Geom &G, const double *x,
+                               const double *u, const double *om, const prs_history *H, int n);
+hipError_t launch_gather_pos(hipStream_t s, const Scratch &S, const Geom &G, const double *x,
+                             int n);
+hipError_t launch_writeback(hipStream_t s, const Scratch &S, double *x, double *u, double *om,
+                            const prs_history *H, double *Fh, double *Th, int n, int buf);
+hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
+
+template <typename T>
+hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const double *templ, const T *gu,
+                               const T *gv, const T *gw, const double *x, const double *up,
+                               const double *om, int n, T *U, T *Ud);
+template <typename T>
+hipError_t launch_spread_plain(hipStream_t s, const Geom &G, const double *templ, const double *x,
+                               int n, const T *F, T *fu, T *fv, T *fw);
+template <typename T>
+hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
+                             const T *f[3], int n, double adt, int iter, int want_den);
+template <typename T>
+hipError_t launch_spread_mdf(hipStream_t s, const Geom &G, const Scratch &S, T *f[3], int n,
+                             const T *F0);
+hipError_t launch_ib_begin(hipStream_t s, const Scratch &S, int n);
+hipError_t launch_slip_reduce(hipStream_t s, const Scratch &S, int n, int iter, int want_den);
+hipError_t launch_ib_finish(hipStream_t s, const Scratch &S, const Geom &G, int n, double rho_f);
+template <typename T>
+hipError_t launch_fill_zero(hipStream_t s, T *p, size_t count);
+
+hipError_t launch_candidates(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
+                             int n, double cut);
+hipError_t launch_substep(hipStream_t s, const Scratch &S, const Geom &G, const Mech &M, int n,
+                          int src, int last);
+hipError_t launch_contact_list(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
+                               int n, int32_t *pairs, long long cap, int phase);
+hipError_t launch_reset_status(hipStream_t s, const Scratch &S);
+
+}  // namespace prs

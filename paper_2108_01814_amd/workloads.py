@@ -262,15 +262,20 @@ def flow_modes(w: Workload, bed_top: float, seed: Optional[int] = None, n_modes:
 
 
 def fluid_field(w: Workload, modes: FlowModes, step: int = 0, device="cpu", dtype=None,
-                out=None):
+                out=None, window=None):
     """Predicted velocity u-hat on the staggered grid at fluid step `step`.
 
     Returns three torch tensors u [Nz, Ny, Nx], v [Nz, Ny+1, Nx], w [Nz, Ny, Nx]
-    (x fastest), computed in float64 and stored in `dtype` on `device`."""
+    (x fastest), computed in float64 and stored in `dtype` on `device`.
+    window = (i0, nx, k0, nz) restricts the output to node columns
+    i0 .. i0+nx-1 and k0 .. k0+nz-1 (the field is periodic, so any integers)."""
     import torch
 
     dtype = dtype or torch.float64
     Nx, Ny, Nz = w.grid
+    i0, k0 = 0, 0
+    if window is not None:
+        i0, Nx, k0, Nz = window
     h = w.h
     Lx, Ly, Lz = w.domain
     t = step * PHYS["dt_f"]
@@ -286,9 +291,9 @@ def fluid_field(w: Workload, modes: FlowModes, step: int = 0, device="cpu", dtyp
         o = [0.5, 0.5, 0.5]
         o[c] = 0.0
         ny_c = Ny + 1 if c == 1 else Ny
-        xs = (torch.arange(Nx, dtype=f64, device=dev) + o[0]) * h
+        xs = (torch.arange(i0, i0 + Nx, dtype=f64, device=dev) + o[0]) * h
         ys = (torch.arange(ny_c, dtype=f64, device=dev) + o[1]) * h
-        zs = (torch.arange(Nz, dtype=f64, device=dev) + o[2]) * h
+        zs = (torch.arange(k0, k0 + Nz, dtype=f64, device=dev) + o[2]) * h
         ax = 2 * math.pi * kx[None, :] * (xs[:, None] - modes.u_c * t) / Lx      # [Nx, m]
         az = 2 * math.pi * kz[None, :] * zs[:, None] / Lz + ph[None, :]         # [Nz, m]
         sy = torch.sin(math.pi * ky[None, :] * ys[:, None] / Ly) * amp[None, :, c]  # [ny, m]

