@@ -195,8 +195,8 @@ def main(argv=None):
     b_interp, b_spread = ib_bytes(w, r32["touched"], 4)
     avg_interp = tm["ms_interp"] / max(tm["n_interp"], 1)
     avg_spread = tm["ms_spread"] / max(tm["n_spread"], 1)
-    kern = {"k_interp_mdf<float>": (b_interp, avg_interp),
-            "k_spread_mdf<float>": (b_spread, avg_spread)}
+    kern = {"prs::k_interp<float, 0, false, 15>": (b_interp, avg_interp),
+            "prs::k_spread_tiles<float, 0>": (b_spread, avg_spread)}
     dom = max(kern, key=lambda k: kern[k][1])
     bts, ms = kern[dom]
     achieved = bts / (ms / 1e3) / 1e9

@@ -166,6 +166,61 @@ hipError_t phase_collect(prs_ctx *c) {
   return hipSuccess;
 }
 
+// Multi-direct forcing on the sorted spheres (Jacobi): every iteration
+// interpolates u** = u-hat + alpha dt f at all markers, then spreads the
+// corrections into f.  In tolerance mode the relative slip of each pass is
+// read back and the loop stops before spreading once it is below tol.
+template <typename T>
+int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *const f[3], int n,
+                const void *F0, bool need_den, int &iters, int &n_slip) {
+  Scratch &S = c->S;
+  const prs_params &q = c->p;
+  const double adt = q.alpha * q.dt_f;
+  const T *uh[3] = {(const T *)uhat[0], (const T *)uhat[1], (const T *)uhat[2]};
+  T *ff[3] = {(T *)f[0], (T *)f[1], (T *)f[2]};
+  const T *fc[3] = {ff[0], ff[1], ff[2]};
+  double *hist_host = c->host_pinned;
+  if (need_den) {
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 1));
+    HIP_TRY(c, phase_end(c, s, kInterp));
+    HIP_TRY(c, launch_slip_reduce(s, S, n, 0, 1));
+  }
+  if (F0) {
+    HIP_TRY(c, launch_marker_sums<T>(s, c->G, S, n, (const T *)F0));
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0));
+    HIP_TRY(c, phase_end(c, s, kSpread));
+  } else {
+    HIP_TRY(c, launch_ib_begin(s, S, n));
+  }
+  const int limit = q.tol_mode ? q.max_iter : q.n_iter;
+  for (int it = 0;; ++it) {
+    if (!q.tol_mode && it >= q.n_iter) break;
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 0));
+    HIP_TRY(c, phase_end(c, s, kInterp));
+    HIP_TRY(c, launch_slip_reduce(s, S, n, it, 0));
+    if (it == 0 && !need_den)
+      HIP_TRY(c, launch_copy_scalar(s, S.slip_hist, S.slip_hist + PRS_MAX_SLIP));
+    n_slip = it + 1;
+    if (q.tol_mode) {
+      HIP_TRY(c, hipMemcpyAsync(hist_host, S.slip_hist, sizeof(double) * (PRS_MAX_SLIP + 1),
+                                hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipStreamSynchronize(s));
+      const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
+      const double rel = den > 0 ? std::sqrt(hist_host[it]) / den : 0.0;
+      if (rel < q.tol || it >= limit) break;
+    }
+    HIP_TRY(c, launch_ft_commit(s, S, n));
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr));
+    HIP_TRY(c, phase_end(c, s, kSpread));
+    iters = it + 1;
+  }
+  return PRS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -218,8 +273,22 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     delete c;
     return PRS_EINVAL;
   }
+  // the interpolation brick of one sphere must fit in the periodic box
+  const int nb = brick_edge(q.radius, q.h);
+  if (q.nx <= nb || q.nz <= nb) {
+    delete c;
+    return PRS_EINVAL;
+  }
   // every argument check above runs before the first HIP call
   (void)hipGetDevice(&c->device);
+  {
+    hipDeviceProp_t prop;
+    const size_t need = (size_t)nb * nb * nb * (q.precision == PRS_F64 ? 8 : 4) + 4096;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && need > prop.sharedMemPerBlock) {
+      delete c;
+      return PRS_EINVAL;
+    }
+  }
   Mech &M = c->M;
   const double R = q.radius;
   M.m = q.rho_p * (4.0 / 3.0) * M_PI * R * R * R;
@@ -263,8 +332,9 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.fh, 3 * n);
   rc |= alloc(c, &S.th, 3 * n);
   rc |= alloc(c, &S.ft_acc, 12 * n);
+  rc |= alloc(c, &S.ft_part, 12 * n);
   rc |= alloc(c, &S.slip_part, 2 * n);
-  rc |= alloc(c, &S.slip_hist, 2 * PRS_MAX_SLIP);
+  rc |= alloc(c, &S.slip_hist, PRS_MAX_SLIP + 1 + 256);
   rc |= alloc(c, &S.ncand, n);
   rc |= alloc(c, &S.cand, (size_t)kCandCap * n);
   rc |= alloc(c, &S.ccount, n + 1);
@@ -275,6 +345,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.status, 4);
   rc |= alloc(c, &S.counters, 4);
   rc |= alloc(c, &S.templ, 3 * (size_t)q.n_markers);
+  rc |= alloc(c, &S.lane_order, (size_t)q.n_markers);
   if (rc != PRS_OK) {
     prs_destroy(c);
     return PRS_EHIP;
@@ -284,7 +355,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     prs_destroy(c);
     return PRS_EHIP;
   }
-  if (launch_template(nullptr, S.templ, q.n_markers) != hipSuccess ||
+  if (launch_template(nullptr, S.templ, S.lane_order, q.n_markers) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     prs_destroy(c);
     return PRS_EHIP;
@@ -326,11 +397,11 @@ int prs_interpolate(prs_ctx *c, void *stream, const void *gu, const void *gv, co
     return fail(c, PRS_EINVAL, "interpolate: Ud needs up and om");
   hipStream_t s = as_stream(stream);
   if (c->p.precision == PRS_F64)
-    HIP_TRY(c, launch_interp_plain<double>(s, c->G, c->S.templ, (const double *)gu,
+    HIP_TRY(c, launch_interp_plain<double>(s, c->G, c->S, (const double *)gu,
                                            (const double *)gv, (const double *)gw, x, up, om, n,
                                            (double *)U, (double *)Ud));
   else
-    HIP_TRY(c, launch_interp_plain<float>(s, c->G, c->S.templ, (const float *)gu,
+    HIP_TRY(c, launch_interp_plain<float>(s, c->G, c->S, (const float *)gu,
                                           (const float *)gv, (const float *)gw, x, up, om, n,
                                           (float *)U, (float *)Ud));
   return PRS_OK;
@@ -344,19 +415,26 @@ int prs_spread(prs_ctx *c, void *stream, const double *x, int32_t n, const void 
   if (n > 0 && (!x || !F)) return fail(c, PRS_EINVAL, "spread: null array");
   hipStream_t s = as_stream(stream);
   void *g[3] = {fu, fv, fw};
+  Scratch &S = c->S;
+  HIP_TRY(c, launch_reset_status(s, S));
   if (c->p.precision == PRS_F64) {
     if (!accumulate)
       for (int k = 0; k < 3; ++k)
         HIP_TRY(c, launch_fill_zero<double>(s, (double *)g[k], grid_count(c, k)));
-    HIP_TRY(c, launch_spread_plain<double>(s, c->G, c->S.templ, x, n, (const double *)F,
-                                           (double *)fu, (double *)fv, (double *)fw));
   } else {
     if (!accumulate)
       for (int k = 0; k < 3; ++k)
         HIP_TRY(c, launch_fill_zero<float>(s, (float *)g[k], grid_count(c, k)));
-    HIP_TRY(c, launch_spread_plain<float>(s, c->G, c->S.templ, x, n, (const float *)F,
-                                          (float *)fu, (float *)fv, (float *)fw));
   }
+  if (n == 0) return PRS_OK;
+  HIP_TRY(c, launch_sort(s, S, c->C_step, c->G, x, n, 0));
+  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n));
+  if (c->p.precision == PRS_F64)
+    HIP_TRY(c, launch_spread_tiles<double>(s, c->G, c->C_step, S, (double **)g, n,
+                                           (const double *)F));
+  else
+    HIP_TRY(c, launch_spread_tiles<float>(s, c->G, c->C_step, S, (float **)g, n,
+                                          (const float *)F));
   return PRS_OK;
 }
 
@@ -430,48 +508,13 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
   int iters = 0, n_slip = 0;
   double *hist_host = c->host_pinned;   // [0..63] slip^2, [64] zero-forcing slip^2
   if (n > 0) {
-    if (F0) {
-      HIP_TRY(c, phase_begin(c, s));
-      if (f64)
-        HIP_TRY(c, launch_spread_mdf<double>(s, c->G, S, (double **)f, n, (const double *)F0));
-      else
-        HIP_TRY(c, launch_spread_mdf<float>(s, c->G, S, (float **)f, n, (const float *)F0));
-      HIP_TRY(c, phase_end(c, s, kSpread));
-    } else {
-      HIP_TRY(c, launch_ib_begin(s, S, n));
-    }
-    const int limit = q.tol_mode ? q.max_iter : q.n_iter;
-    for (int it = 0;; ++it) {
-      if (!q.tol_mode && it >= q.n_iter) break;
-      HIP_TRY(c, phase_begin(c, s));
-      if (f64)
-        HIP_TRY(c, launch_interp_mdf<double>(s, c->G, S, (const double **)uhat,
-                                             (const double **)f, n, adt, it, it == 0));
-      else
-        HIP_TRY(c, launch_interp_mdf<float>(s, c->G, S, (const float **)uhat, (const float **)f,
-                                            n, adt, it, it == 0));
-      HIP_TRY(c, phase_end(c, s, kInterp));
-      HIP_TRY(c, launch_slip_reduce(s, S, n, it, it == 0));
-      n_slip = it + 1;
-      if (q.tol_mode) {
-        HIP_TRY(c, hipMemcpyAsync(hist_host + it, S.slip_hist + it, sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-        if (it == 0)
-          HIP_TRY(c, hipMemcpyAsync(hist_host + PRS_MAX_SLIP, S.slip_hist + PRS_MAX_SLIP,
-                                    sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
-        const double rel = den > 0 ? std::sqrt(hist_host[it]) / den : 0.0;
-        if (rel < q.tol || it >= limit) break;
-      }
-      HIP_TRY(c, phase_begin(c, s));
-      if (f64)
-        HIP_TRY(c, launch_spread_mdf<double>(s, c->G, S, (double **)f, n, nullptr));
-      else
-        HIP_TRY(c, launch_spread_mdf<float>(s, c->G, S, (float **)f, n, nullptr));
-      HIP_TRY(c, phase_end(c, s, kSpread));
-      iters = it + 1;
-    }
+    // the first pass sees f = 0 only when the field was cleared here and no
+    // initial marker force is spread; otherwise the zero-forcing slip needs a
+    // pass of its own
+    const bool need_den = !zero_f || F0 != nullptr;
+    const int rc = f64 ? run_forcing<double>(c, s, uhat, f, n, F0, need_den, iters, n_slip)
+                       : run_forcing<float>(c, s, uhat, f, n, F0, need_den, iters, n_slip);
+    if (rc != PRS_OK) return rc;
     HIP_TRY(c, launch_ib_finish(s, S, c->G, n, q.rho_f));
 
     // ---- contacts and Newton-Euler substeps ----

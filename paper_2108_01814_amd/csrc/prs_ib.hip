@@ -1,20 +1,33 @@
 // Immersed-boundary kernels: marker template, interpolation of the staggered
-// fluid velocity at the Lagrangian markers, the direct-forcing correction,
-// and diffusion (spreading) of marker forces back to the grid (sec. 3.3 and
-// eq. 4 of the paper; the regularised delta function is the three-point
-// kernel, the iteration is multi-direct forcing in Jacobi form).
+// fluid velocity at the Lagrangian markers with the direct-forcing
+// correction, and diffusion (spreading) of marker forces back to the grid
+// (sec. 3.3 and eq. 4 of the paper; the regularised delta function is the
+// three-point kernel, the iteration is multi-direct forcing in Jacobi form).
 //
-// Work decomposition: one workgroup per sphere, one lane per marker, so
-// every workgroup carries the same number of markers however dense the bed
-// is around it (the marker-based balancing of sec. 3.3 on one GPU), and the
-// per-sphere force and torque are workgroup reductions.
-#include "prs_device.h"
+// Interpolation: one workgroup per sphere, one lane per marker, so every
+// workgroup carries the same number of markers however dense the bed is
+// around it (the marker-based balancing of sec. 3.3 on one GPU).  The grid
+// brick around the sphere is staged in LDS (one velocity component at a time
+// unless all three fit in PRS_BRICK_ALL3_MAX_BYTES) with coalesced row loads;
+// the 27-point stencils then read LDS only.
+//
+// Spreading: one workgroup per grid tile.  The tile gathers the spheres whose
+// markers can reach it from the cell list, accumulates their contributions to
+// the tile's own nodes with LDS atomics (double-precision accumulators), and
+// adds the tile to the force field
+// with plain coalesced read-modify-writes.  Every grid node belongs to exactly
+// one tile, so no global atomics are needed.
+#include <type_traits>
+
+#include "prs_stencil.h"
 
 namespace prs {
 
 // ---------------------------------------------------------------------------
 // template
 // ---------------------------------------------------------------------------
+// Fibonacci sphere, pole along y.  The y-component 1 - (2l+1)/N decreases
+// with l, which the spreading kernel uses to cull markers by height.
 __global__ void k_template(double *t, int nl) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nl) return;
@@ -27,395 +40,632 @@ __global__ void k_template(double *t, int nl) {
   t[3 * l + 2] = rho * sin(th);
 }
 
-hipError_t launch_template(hipStream_t s, double *t, int nl) {
+// Lane order of the interpolation workgroup: within every aligned chunk of
+// 64 markers (a band of nearly equal height, the template's y-component being
+// monotone in l) sort by azimuth, so the lanes of one wave handle neighbouring
+// markers and their stencil reads from LDS mostly coincide or sit side by side.
+__global__ void k_lane_order(const double *t, int nl, int *order) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  const int c0 = (l / 64) * 64, c1 = min(c0 + 64, nl);
+  const double al = atan2(t[3 * l + 2], t[3 * l + 0]);
+  int rank = 0;
+  for (int m = c0; m < c1; ++m) {
+    const double am = atan2(t[3 * m + 2], t[3 * m + 0]);
+    if (am < al || (am == al && m < l)) ++rank;
+  }
+  order[c0 + rank] = l;
+}
+
+hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl) {
   hipLaunchKernelGGL(k_template, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl);
+  hipLaunchKernelGGL(k_lane_order, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl, lane_order);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// stencil of one marker for one staggered component
-// ---------------------------------------------------------------------------
-// Three-point kernel weights of the nodes ic-1, ic, ic+1 for the offset
-// r0 = s - ic in [-1/2, 1/2) (s in node units): with q = sqrt(1 - 3 r0^2),
-// w(ic) = (1+q)/3 and w(ic+-1) = (2 +- 3 r0 - q)/6.
-template <typename T>
-__device__ inline void kernel3(double s, int &ic, T w[3]) {
-  const double c = floor(s + 0.5);
-  ic = (int)c;
-  const T r = (T)(s - c);
-  const T q = sqrt((T)1 - (T)3 * r * r);
-  w[0] = ((T)2 - (T)3 * r - q) * (T)(1.0 / 6.0);
-  w[1] = ((T)1 + q) * (T)(1.0 / 3.0);
-  w[2] = ((T)2 + (T)3 * r - q) * (T)(1.0 / 6.0);
-}
-
-template <typename T>
-struct Stencil {
-  int ix[3];
-  int kz[3];
-  int j0;        // first row (may be out of range; masked by jok)
-  bool jok[3];
-  T wx[3], wy[3], wz[3];
-  int nyc;
-};
-
-template <typename T>
-__device__ inline void make_stencil(const Geom &G, int c, const double X[3], Stencil<T> &S) {
-  const double ox = c == 0 ? 0.0 : 0.5, oy = c == 1 ? 0.0 : 0.5, oz = c == 2 ? 0.0 : 0.5;
-  int icx, icy, icz;
-  kernel3<T>(X[0] * G.inv_h - ox, icx, S.wx);
-  kernel3<T>(X[1] * G.inv_h - oy, icy, S.wy);
-  kernel3<T>(X[2] * G.inv_h - oz, icz, S.wz);
-  for (int a = 0; a < 3; ++a) {
-    S.ix[a] = wrap_once(icx - 1 + a, G.nx);
-    S.kz[a] = wrap_once(icz - 1 + a, G.nz);
-  }
-  S.j0 = icy - 1;
-  const int jlo = (c == 1) ? 1 : 0;
-  for (int a = 0; a < 3; ++a) {
-    const int j = S.j0 + a;
-    S.jok[a] = (j >= jlo) && (j <= G.ny - 1);
-  }
-  S.nyc = G.ny + (c == 1 ? 1 : 0);
-}
-
-// a1 = I[g1], a2 = I[g2] (g2 may be null).
-template <typename T, bool TWO>
-__device__ inline void gather(const Geom &G, const Stencil<T> &S, const T *__restrict__ g1,
-                              const T *__restrict__ g2, T &a1, T &a2) {
-  T s1 = 0, s2 = 0;
-#pragma unroll
-  for (int kk = 0; kk < 3; ++kk) {
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      if (!S.jok[jj]) continue;
-      const size_t row = ((size_t)S.kz[kk] * S.nyc + (size_t)(S.j0 + jj)) * (size_t)G.nx;
-      const T wzy = S.wz[kk] * S.wy[jj];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        const T w = wzy * S.wx[ii];
-        s1 += g1[row + S.ix[ii]] * w;
-        if (TWO) s2 += g2[row + S.ix[ii]] * w;
-      }
-    }
-  }
-  a1 = s1;
-  a2 = s2;
-}
-
-template <typename T>
-__device__ inline void scatter(const Geom &G, const Stencil<T> &S, T *__restrict__ g, T val) {
-#pragma unroll
-  for (int kk = 0; kk < 3; ++kk) {
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      if (!S.jok[jj]) continue;
-      const size_t row = ((size_t)S.kz[kk] * S.nyc + (size_t)(S.j0 + jj)) * (size_t)G.nx;
-      const T wzy = S.wz[kk] * S.wy[jj];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) atomicAdd(&g[row + S.ix[ii]], val * (wzy * S.wx[ii]));
-    }
-  }
-}
-
-__device__ inline void load_sphere_aos(const Geom &G, const double *x, const double *up,
-                                       const double *om, int p, double xp[3], double u[3],
-                                       double w[3]) {
-  uint32_t fl = 0;
-  xp[0] = sane_coord(x[3 * p + 0], G.Lx, false, fl);
-  xp[1] = sane_coord(x[3 * p + 1], G.Ly, true, fl);
-  xp[2] = sane_coord(x[3 * p + 2], G.Lz, false, fl);
-  for (int a = 0; a < 3; ++a) {
-    u[a] = up ? up[3 * p + a] : 0.0;
-    w[a] = om ? om[3 * p + a] : 0.0;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// plain interpolation / spreading (caller order, one field set)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(1024) void k_interp_plain(Geom G, const double *__restrict__ templ,
-                                                       const T *__restrict__ gu,
-                                                       const T *__restrict__ gv,
-                                                       const T *__restrict__ gw,
-                                                       const double *x, const double *up,
-                                                       const double *om, int n, T *U, T *Ud) {
-  const int p = xcd_item(blockIdx.x, n);
-  const int l = threadIdx.x;
-  if (p < 0 || l >= G.nl) return;
-  double xp[3], u[3], w[3];
-  load_sphere_aos(G, x, up, om, p, xp, u, w);
-  const double r[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
-  const double X[3] = {xp[0] + r[0], xp[1] + r[1], xp[2] + r[2]};
-  const T *g[3] = {gu, gv, gw};
-  const size_t m = (size_t)p * G.nl + l;
-  for (int c = 0; c < 3; ++c) {
-    Stencil<T> S;
-    make_stencil<T>(G, c, X, S);
-    T a, b;
-    gather<T, false>(G, S, g[c], nullptr, a, b);
-    U[3 * m + c] = a;
-  }
-  if (Ud) {
-    Ud[3 * m + 0] = (T)(u[0] + (w[1] * r[2] - w[2] * r[1]));
-    Ud[3 * m + 1] = (T)(u[1] + (w[2] * r[0] - w[0] * r[2]));
-    Ud[3 * m + 2] = (T)(u[2] + (w[0] * r[1] - w[1] * r[0]));
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_spread_plain(Geom G, const double *__restrict__ templ,
-                                                       const double *x, int n,
-                                                       const T *__restrict__ F, T *fu, T *fv,
-                                                       T *fw) {
-  const int p = xcd_item(blockIdx.x, n);
-  const int l = threadIdx.x;
-  if (p < 0 || l >= G.nl) return;
-  double xp[3], u[3], w[3];
-  load_sphere_aos(G, x, nullptr, nullptr, p, xp, u, w);
-  const double X[3] = {xp[0] + G.R * templ[3 * l], xp[1] + G.R * templ[3 * l + 1],
-                       xp[2] + G.R * templ[3 * l + 2]};
-  const T scale = (T)(G.dV * G.inv_h * G.inv_h * G.inv_h);
-  T *g[3] = {fu, fv, fw};
-  const size_t m = (size_t)p * G.nl + l;
-  for (int c = 0; c < 3; ++c) {
-    Stencil<T> S;
-    make_stencil<T>(G, c, X, S);
-    scatter<T>(G, S, g[c], F[3 * m + c] * scale);
-  }
-}
+int brick_edge(double R, double h) { return (int)std::ceil(2.0 * R / h) + 5; }
 
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
-template <typename T>
-hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const double *templ, const T *gu,
-                               const T *gv, const T *gw, const double *x, const double *up,
-                               const double *om, int n, T *U, T *Ud) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_plain<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G, templ,
-                     gu, gv, gw, x, up, om, n, U, Ud);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_spread_plain(hipStream_t s, const Geom &G, const double *templ, const double *x,
-                               int n, const T *F, T *fu, T *fv, T *fw) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spread_plain<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G, templ,
-                     x, n, F, fu, fv, fw);
-  return hipGetLastError();
-}
-
-template hipError_t launch_interp_plain<float>(hipStream_t, const Geom &, const double *,
-                                               const float *, const float *, const float *,
-                                               const double *, const double *, const double *,
-                                               int, float *, float *);
-template hipError_t launch_interp_plain<double>(hipStream_t, const Geom &, const double *,
-                                                const double *, const double *, const double *,
-                                                const double *, const double *, const double *,
-                                                int, double *, double *);
-template hipError_t launch_spread_plain<float>(hipStream_t, const Geom &, const double *,
-                                               const double *, int, const float *, float *,
-                                               float *, float *);
-template hipError_t launch_spread_plain<double>(hipStream_t, const Geom &, const double *,
-                                                const double *, int, const double *, double *,
-                                                double *, double *);
-
 // ---------------------------------------------------------------------------
-// block reduction of the per-marker force/torque and slip contributions
+// interpolation with an LDS brick per sphere
 // ---------------------------------------------------------------------------
-// v: 6 compensated pairs (force, torque) + 2 plain sums (slip^2, zero-forcing
-// slip^2).  Result valid in thread 0.
-struct Red {
-  double s[6], c[6];
-  double q[2];
+enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2 };
+
+// MODE kInterpMDF  : sorted SoA state; u** = a + adt*b; writes dF [3][M],
+//                    the slip partial and the force/torque partials.
+// MODE kInterpDen  : sorted SoA state; a only; writes the zero-forcing slip
+//                    partial ||U_d - I[a]||^2.
+// MODE kInterpPlain: caller-order AoS positions; a only; writes U [n][nl][3]
+//                    and optionally U_d.
+// Brick rows loaded per lane before the LDS stores (measured on MI355X at
+// D/h = 10: 2 is best for single precision, 4 for double).
+#ifndef PRS_BRICK_UNROLL_F32
+#define PRS_BRICK_UNROLL_F32 2
+#endif
+#ifndef PRS_BRICK_UNROLL_F64
+#define PRS_BRICK_UNROLL_F64 4
+#endif
+#ifndef PRS_BRICK_ALL3_MAX_BYTES
+#define PRS_BRICK_ALL3_MAX_BYTES 0
+#endif
+template <typename T>
+struct BrickUnroll {
+  static constexpr int value = sizeof(T) == 4 ? PRS_BRICK_UNROLL_F32 : PRS_BRICK_UNROLL_F64;
 };
 
-__device__ inline void wave_reduce(Red &r) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const double s2 = __shfl_xor(r.s[k], off);
-      const double c2 = __shfl_xor(r.c[k], off);
-      comp_add(r.s[k], r.c[k], s2, c2);
-    }
-    r.q[0] += __shfl_xor(r.q[0], off);
-    r.q[1] += __shfl_xor(r.q[1], off);
-  }
-}
-
-__device__ inline void block_reduce(Red &r) {
-  __shared__ double lds[16][14];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  wave_reduce(r);
-  if (lane == 0) {
-    for (int k = 0; k < 6; ++k) {
-      lds[wave][k] = r.s[k];
-      lds[wave][6 + k] = r.c[k];
-    }
-    lds[wave][12] = r.q[0];
-    lds[wave][13] = r.q[1];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int wv = 1; wv < nw; ++wv) {
-      for (int k = 0; k < 6; ++k) comp_add(r.s[k], r.c[k], lds[wv][k], lds[wv][6 + k]);
-      r.q[0] += lds[wv][12];
-      r.q[1] += lds[wv][13];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// multi-direct forcing on the sorted spheres
-// ---------------------------------------------------------------------------
-// Interpolation pass of one iteration.  u** = u-hat + alpha dt f is formed on
-// the fly from the two fields.  Per marker: U = I[u**], r = U_d - U,
-// dF = r/(alpha dt) stored for the spreading pass; per sphere: the slip
-// partials (sum of r^2, and of (U_d - I[u-hat])^2 for the relative slip).
-template <typename T>
-__global__ __launch_bounds__(1024) void k_interp_mdf(
-    Geom G, const double *__restrict__ templ, const T *__restrict__ uh0,
-    const T *__restrict__ uh1, const T *__restrict__ uh2, const T *__restrict__ f0,
-    const T *__restrict__ f1, const T *__restrict__ f2, const double *__restrict__ xs,
-    const double *__restrict__ us, const double *__restrict__ ws, int n, double adt,
-    T *__restrict__ dF, double *__restrict__ slip_part) {
+// NB > 0: brick edge known at compile time (the index arithmetic of the brick
+// loads then needs no integer divisions); NB == 0: runtime edge nb.
+template <typename T, int MODE, bool ALL3, int NB>
+__global__ __launch_bounds__(1024) void k_interp(
+    Geom G, const double *__restrict__ templ, const T *__restrict__ a0, const T *__restrict__ a1,
+    const T *__restrict__ a2, const T *__restrict__ b0, const T *__restrict__ b1,
+    const T *__restrict__ b2, double adt, const double *__restrict__ xs,
+    const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
+    T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
+    double *__restrict__ ft_part, const int *__restrict__ order) {
+  extern __shared__ unsigned char smem_raw[];
+  T *brick = reinterpret_cast<T *>(smem_raw);
+  if (NB > 0) nb = NB;
   const int p = xcd_item(blockIdx.x, n);
   if (p < 0) return;
-  const int l = threadIdx.x;
-  Red red;
-  for (int k = 0; k < 6; ++k) red.s[k] = red.c[k] = 0.0;
-  red.q[0] = red.q[1] = 0.0;
-  if (l < G.nl) {
-    const double r[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
-    const double X[3] = {xs[p] + r[0], xs[n + p] + r[1], xs[2 * n + p] + r[2]};
-    const double w[3] = {ws[p], ws[n + p], ws[2 * n + p]};
-    const double Ud[3] = {us[p] + (w[1] * r[2] - w[2] * r[1]),
-                          us[n + p] + (w[2] * r[0] - w[0] * r[2]),
-                          us[2 * n + p] + (w[0] * r[1] - w[1] * r[0])};
-    const T *uh[3] = {uh0, uh1, uh2};
-    const T *ff[3] = {f0, f1, f2};
-    const size_t M = (size_t)n * G.nl;
-    const size_t m = (size_t)p * G.nl + l;
-    const T tadt = (T)adt;
-    for (int c = 0; c < 3; ++c) {
-      Stencil<T> S;
-      make_stencil<T>(G, c, X, S);
-      T iu, ifc;
-      gather<T, true>(G, S, uh[c], ff[c], iu, ifc);
-      const T U = iu + tadt * ifc;
-      const T res = (T)Ud[c] - U;
-      const T corr = res / tadt;
-      dF[c * M + m] = corr;
-      red.q[0] += (double)res * (double)res;
-      const double z = Ud[c] - (double)iu;
-      red.q[1] += z * z;
-    }
-  }
-  block_reduce(red);
-  if (threadIdx.x == 0) {
-    slip_part[p] = red.q[0];
-    slip_part[n + p] = red.q[1];
-  }
-}
+  const bool active = (int)threadIdx.x < G.nl;
+  const int l = active ? order[threadIdx.x] : 0;
+  const size_t N = (size_t)n;
 
-// Spreading pass: f += S[dF] (sorted spheres, corrections from the buffer),
-// and the compensated per-sphere sums of dF and (R t) x dF added to the
-// force/torque accumulators; or, with F0 != null, the spread of a
-// caller-ordered initial marker force whose sums seed the accumulators.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_spread_mdf(Geom G, const double *__restrict__ templ,
-                                                     const double *__restrict__ xs, int n,
-                                                     const T *__restrict__ dF,
-                                                     const T *__restrict__ F0,
-                                                     const int *__restrict__ perm, T *f0, T *f1,
-                                                     T *f2, double *__restrict__ acc) {
-  const int p = xcd_item(blockIdx.x, n);
-  if (p < 0) return;
-  const int l = threadIdx.x;
-  Red red;
-  for (int k = 0; k < 6; ++k) red.s[k] = red.c[k] = 0.0;
-  red.q[0] = red.q[1] = 0.0;
-  if (l < G.nl) {
-    const double r[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
-    const double X[3] = {xs[p] + r[0], xs[n + p] + r[1], xs[2 * n + p] + r[2]};
-    const size_t M = (size_t)n * G.nl;
-    T v[3];
-    if (F0) {
-      const size_t mc = (size_t)perm[p] * G.nl + l;
-      for (int c = 0; c < 3; ++c) v[c] = F0[3 * mc + c];
-    } else {
-      const size_t m = (size_t)p * G.nl + l;
-      for (int c = 0; c < 3; ++c) v[c] = dF[c * M + m];
-    }
-    const T scale = (T)(G.dV * G.inv_h * G.inv_h * G.inv_h);
-    T *g[3] = {f0, f1, f2};
-    for (int c = 0; c < 3; ++c) {
-      Stencil<T> S;
-      make_stencil<T>(G, c, X, S);
-      scatter<T>(G, S, g[c], v[c] * scale);
-    }
-    const double d[3] = {(double)v[0], (double)v[1], (double)v[2]};
-    red.s[0] = d[0];
-    red.s[1] = d[1];
-    red.s[2] = d[2];
-    red.s[3] = r[1] * d[2] - r[2] * d[1];
-    red.s[4] = r[2] * d[0] - r[0] * d[2];
-    red.s[5] = r[0] * d[1] - r[1] * d[0];
-  }
-  block_reduce(red);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 6; ++k) {
-      double S = 0.0, C = 0.0;
-      if (!F0) {
-        S = acc[(2 * k) * (size_t)n + p];
-        C = acc[(2 * k + 1) * (size_t)n + p];
+  double xp[3], up[3] = {0, 0, 0}, wp[3] = {0, 0, 0};
+  if (MODE == kInterpPlain) {
+    uint32_t fl = 0;
+    xp[0] = sane_coord(xs[3 * p + 0], G.Lx, false, fl);
+    xp[1] = sane_coord(xs[3 * p + 1], G.Ly, true, fl);
+    xp[2] = sane_coord(xs[3 * p + 2], G.Lz, false, fl);
+    if (out2)
+      for (int a = 0; a < 3; ++a) {
+        up[a] = us[3 * p + a];
+        wp[a] = ws[3 * p + a];
       }
-      comp_add(S, C, red.s[k], red.c[k]);
-      acc[(2 * k) * (size_t)n + p] = S;
-      acc[(2 * k + 1) * (size_t)n + p] = C;
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      xp[a] = xs[a * N + p];
+      up[a] = us[a * N + p];
+      wp[a] = ws[a * N + p];
     }
   }
+  double rl[3] = {0, 0, 0}, X[3] = {0, 0, 0};
+  if (active)
+    for (int a = 0; a < 3; ++a) {
+      rl[a] = G.R * templ[3 * l + a];
+      X[a] = xp[a] + rl[a];
+    }
+  const double Ud[3] = {up[0] + (wp[1] * rl[2] - wp[2] * rl[1]),
+                        up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
+                        up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
+  const T tadt = (T)adt;
+  const int nb2 = nb * nb, nb3 = nb2 * nb;
+  int lo[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) lo[c][a] = brick_lo(xp[a], G.R, G.inv_h, stagger(c, a)) - 1;
+  T U[3] = {(T)0, (T)0, (T)0};
+  // ALL3: the bricks of the three components are staged together; otherwise
+  // one component at a time.
+  for (int pass = 0; pass < (ALL3 ? 1 : 3); ++pass) {
+    const int c0 = ALL3 ? 0 : pass, nc = ALL3 ? 3 : 1;
+    const int total = nc * nb3;
+    __syncthreads();   // the previous pass's brick is no longer read
+    // x-rows of the brick: XL lanes per row (nb rounded up to a power of two),
+    // so the index arithmetic is done per row rather than per element
+    (void)total;
+    const int XL = nb <= 16 ? 16 : (nb <= 32 ? 32 : 64);
+    const int bx = threadIdx.x & (XL - 1);
+    const int rows_per = blockDim.x / XL;
+    const int nrows = nc * nb2;
+    constexpr int kBrickUnroll = BrickUnroll<T>::value;
+    for (int row0 = threadIdx.x / XL; row0 < nrows; row0 += rows_per * kBrickUnroll) {
+      T v[kBrickUnroll];
+#pragma unroll
+      for (int u = 0; u < kBrickUnroll; ++u) {
+        const int row = row0 + u * rows_per;
+        v[u] = (T)0;
+        if (row < nrows && bx < nb) {
+          const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
+          const int rr = row - cc * nb2;
+          const int bz = rr / nb, by = rr - bz * nb;
+          const int j = lo[c][1] + by;
+          if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
+            const int i = wrap_once(lo[c][0] + bx, G.nx), k = wrap_once(lo[c][2] + bz, G.nz);
+            const int nyc = G.ny + (c == 1 ? 1 : 0);
+            const size_t g = ((size_t)k * nyc + j) * G.nx + i;
+            const T *Ap = c == 0 ? a0 : (c == 1 ? a1 : a2);
+            v[u] = Ap[g];
+            if (MODE == kInterpMDF) {
+              const T *Bp = c == 0 ? b0 : (c == 1 ? b1 : b2);
+              v[u] += tadt * Bp[g];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBrickUnroll; ++u) {
+        const int row = row0 + u * rows_per;
+        if (row < nrows && bx < nb) brick[row * nb + bx] = v[u];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int cc = 0; cc < nc; ++cc) {
+        const int c = c0 + cc;
+        Stencil<T> S;
+        make_stencil<T>(G, c, X, S);
+        int b[3];
+        for (int a = 0; a < 3; ++a) b[a] = min(max(S.ic[a] - 1 - lo[c][a], 0), nb - 3);
+        const T *bk = brick + cc * nb3;
+        T sum = 0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) {
+            const T wzy = S.w[2][kk] * S.w[1][jj];
+            const T *row = bk + ((b[2] + kk) * nb + (b[1] + jj)) * nb + b[0];
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) sum += row[ii] * (wzy * S.w[0][ii]);
+          }
+        U[c] = sum;
+      }
+    }
+  }
+
+  if (MODE == kInterpPlain) {
+    if (active) {
+      const size_t m = (size_t)p * G.nl + l;
+      for (int c = 0; c < 3; ++c) out[3 * m + c] = U[c];
+      if (out2)
+        for (int c = 0; c < 3; ++c) out2[3 * m + c] = (T)Ud[c];
+    }
+    return;
+  }
+  Red red;
+  red_zero(red);
+  if (active) {
+    if (MODE == kInterpMDF) {
+      const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        const T res = (T)Ud[c] - U[c];
+        const T corr = res / tadt;
+        out[c * M + m] = corr;
+        d[c] = (double)corr;
+        red.q[0] += (double)res * (double)res;
+      }
+      red_set_ft(red, rl, d);
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        const double z = Ud[c] - (double)U[c];
+        red.q[1] += z * z;
+      }
+    }
+  }
+  block_reduce(red);
+  if (threadIdx.x == 0) {
+    if (MODE == kInterpMDF) {
+      slip_part[p] = red.q[0];
+      for (int k = 0; k < 6; ++k) {
+        ft_part[(2 * k) * N + p] = red.s[k];
+        ft_part[(2 * k + 1) * N + p] = red.c[k];
+      }
+    } else {
+      slip_part[N + p] = red.q[1];
+    }
+  }
+}
+
+// Launch k_interp with the brick edge as a compile-time constant when it is
+// one of the common sizes (D/h = 10 -> 15, D/h = 16 -> 21).
+template <typename T, int MODE, bool ALL3>
+void launch_interp_nb(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Geom &G,
+                      const double *templ, const T *a0, const T *a1, const T *a2, const T *b0,
+                      const T *b1, const T *b2, double adt, const double *xs, const double *us,
+                      const double *ws, int n, int nb, T *out, T *out2, double *slip_part,
+                      double *ft_part, const int *order) {
+  if (nb == 15)
+    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 15>), grid, block, lds, s, G, templ, a0, a1, a2,
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+  else if (nb == 21)
+    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 21>), grid, block, lds, s, G, templ, a0, a1, a2,
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+  else
+    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 0>), grid, block, lds, s, G, templ, a0, a1, a2,
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+}
+
+template <typename T, int MODE>
+hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, const T *a0,
+                             const T *a1, const T *a2, const T *b0, const T *b1, const T *b2,
+                             double adt, const double *xs, const double *us, const double *ws,
+                             int n, T *out, T *out2, double *slip_part, double *ft_part,
+                             const int *order) {
+  if (n == 0) return hipSuccess;
+  const int nb = brick_edge(G.R, G.h);
+  const size_t one = sizeof(T) * nb * nb * nb;
+  const bool all3 = 3 * one <= PRS_BRICK_ALL3_MAX_BYTES;
+  const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
+  if (all3)
+    launch_interp_nb<T, MODE, true>(grid, block, 3 * one, s, G, templ, a0, a1, a2, b0, b1, b2,
+                                    adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+  else
+    launch_interp_nb<T, MODE, false>(grid, block, one, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
+                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, const T *gu,
+                               const T *gv, const T *gw, const double *x, const double *up,
+                               const double *om, int n, T *U, T *Ud) {
+  return launch_interp_any<T, kInterpPlain>(s, G, S.templ, gu, gv, gw, nullptr, nullptr, nullptr,
+                                            0.0, x, up, om, n, U, Ud, nullptr, nullptr,
+                                            S.lane_order);
 }
 
 template <typename T>
 hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
-                             const T *f[3], int n, double adt, int iter, int want_den) {
-  (void)iter;
-  (void)want_den;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_interp_mdf<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G, S.templ,
-                     uh[0], uh[1], uh[2], f[0], f[1], f[2], S.xs[0], S.us[0], S.ws[0], n, adt,
-                     (T *)S.dF, S.slip_part);
-  return hipGetLastError();
+                             const T *f[3], int n, double adt, int den_only) {
+  if (den_only)
+    return launch_interp_any<T, kInterpDen>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+                                            nullptr, adt, S.xs[0], S.us[0], S.ws[0], n, nullptr,
+                                            nullptr, S.slip_part, nullptr, S.lane_order);
+  return launch_interp_any<T, kInterpMDF>(s, G, S.templ, uh[0], uh[1], uh[2], f[0], f[1], f[2],
+                                          adt, S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
+                                          S.slip_part, S.ft_part, S.lane_order);
+}
+
+template hipError_t launch_interp_plain<float>(hipStream_t, const Geom &, const Scratch &,
+                                               const float *, const float *, const float *,
+                                               const double *, const double *, const double *,
+                                               int, float *, float *);
+template hipError_t launch_interp_plain<double>(hipStream_t, const Geom &, const Scratch &,
+                                                const double *, const double *, const double *,
+                                                const double *, const double *, const double *,
+                                                int, double *, double *);
+template hipError_t launch_interp_mdf<float>(hipStream_t, const Geom &, const Scratch &,
+                                             const float *[3], const float *[3], int, double, int);
+template hipError_t launch_interp_mdf<double>(hipStream_t, const Geom &, const Scratch &,
+                                              const double *[3], const double *[3], int, double,
+                                              int);
+
+// ---------------------------------------------------------------------------
+// spreading by grid tiles
+// ---------------------------------------------------------------------------
+// Tile shapes (nodes per axis) and workgroup size; compile-time tuning knobs.
+#ifndef PRS_TILE_F32
+#define PRS_TILE_F32 16, 8, 16
+#endif
+#ifndef PRS_TILE_F64
+#define PRS_TILE_F64 16, 8, 16
+#endif
+#ifndef PRS_TILE_THREADS
+#define PRS_TILE_THREADS 512
+#endif
+
+template <int TX_, int TY_, int TZ_>
+struct Shape3 {
+  static constexpr int X = TX_, Y = TY_, Z = TZ_;
+};
+template <typename T>
+struct TileShape;
+template <>
+struct TileShape<float> : Shape3<PRS_TILE_F32> {};
+template <>
+struct TileShape<double> : Shape3<PRS_TILE_F64> {};
+
+// Accumulate the tiles of single-precision fields in double-precision LDS:
+// on gfx950 the LDS double-precision atomic add sustains about three times
+// the rate of the single-precision one in this access pattern (and the sums
+// are more accurate).
+#ifndef PRS_SPREAD_ACC_F64
+#define PRS_SPREAD_ACC_F64 1
+#endif
+template <typename T>
+struct TileAcc {
+  using type = T;
+};
+template <>
+struct TileAcc<float> {
+  using type = typename std::conditional<PRS_SPREAD_ACC_F64 != 0, double, float>::type;
+};
+
+constexpr int kTileCand = 256;     // spheres gathered by one tile
+constexpr int kTileThreads = PRS_TILE_THREADS;
+static_assert(kTileThreads >= kTileCand, "one scan lane per candidate");
+
+// SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
+//        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
+//        sorted order read at perm[k].
+template <typename T, int SRC>
+__global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
+    Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
+    const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
+    T *f0, T *f1, T *f2, uint32_t *status) {
+  constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
+  constexpr int NODES = TX * TY * TZ;
+  using A_t = typename TileAcc<T>::type;
+  __shared__ A_t acc[3 * NODES];
+  __shared__ int c_idx[kTileCand];
+  __shared__ int c_l0[kTileCand];
+  __shared__ int c_pref[kTileCand + 1];
+  __shared__ double c_x[kTileCand][3];
+  __shared__ int c_n;
+
+  const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + 1 + TY - 1) / TY,
+            ntz = (G.nz + TZ - 1) / TZ;
+  const int tile = xcd_item(blockIdx.x, ntx * nty * ntz);
+  if (tile < 0) return;
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int i0 = tx * TX, j0 = ty * TY, k0 = tz * TZ;
+  const double h = G.h, R = G.R;
+  const size_t N = (size_t)n;
+
+  // Sphere centres whose markers can reach the tile's nodes: a marker reaches
+  // node i of a component when |X/h - o - i| < 3/2, i.e. X/h in
+  // (i0 - 3/2, i0 + T + 1) over the tile and both staggerings.
+  const double lo[3] = {(i0 - 1.5) * h - R, (j0 - 1.5) * h - R, (k0 - 1.5) * h - R};
+  const double hi[3] = {(i0 + TX + 1.0) * h + R, (j0 + TY + 1.0) * h + R,
+                        (k0 + TZ + 1.0) * h + R};
+  const double ctr[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+  const double hw[3] = {0.5 * (hi[0] - lo[0]) + 1e-9, 0.5 * (hi[1] - lo[1]) + 1e-9,
+                        0.5 * (hi[2] - lo[2]) + 1e-9};
+  // the same box for the markers themselves (no sphere radius)
+  const double mctr[3] = {(i0 + 0.5 * (TX - 0.5)) * h, (j0 + 0.5 * (TY - 0.5)) * h,
+                          (k0 + 0.5 * (TZ - 0.5)) * h};
+  const double mhw[3] = {(0.5 * TX + 1.25) * h + 1e-9 * h, (0.5 * TY + 1.25) * h + 1e-9 * h,
+                         (0.5 * TZ + 1.25) * h + 1e-9 * h};
+
+  if (threadIdx.x == 0) c_n = 0;
+  __syncthreads();
+  {
+    const int cxl = (int)floor(lo[0] / C.csx), cxh = (int)floor(hi[0] / C.csx);
+    const int czl = (int)floor(lo[2] / C.csz), czh = (int)floor(hi[2] / C.csz);
+    const int cyl = max((int)floor(lo[1] / C.csy), 0), cyh = min((int)floor(hi[1] / C.csy), C.ncy - 1);
+    const int nxc = min(cxh - cxl + 1, C.ncx), nzc = min(czh - czl + 1, C.ncz);
+    const int nyc = cyh - cyl + 1;
+    const int ncell = nyc > 0 ? nxc * nyc * nzc : 0;
+    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+      const int qx = q % nxc, qy = (q / nxc) % nyc, qz = q / (nxc * nyc);
+      int cx = (cxl + qx) % C.ncx;
+      if (cx < 0) cx += C.ncx;
+      int cz = (czl + qz) % C.ncz;
+      if (cz < 0) cz += C.ncz;
+      const int key = cell_key(C, cx, cyl + qy, cz);
+      const int e = start[key + 1];
+      for (int k = start[key]; k < e; ++k) {
+        const double px = xs[k], py = xs[N + k], pz = xs[2 * N + k];
+        if (fabs(min_image(px - ctr[0], G.Lx)) > hw[0] || fabs(py - ctr[1]) > hw[1] ||
+            fabs(min_image(pz - ctr[2], G.Lz)) > hw[2])
+          continue;
+        const int slot = atomicAdd(&c_n, 1);
+        if (slot < kTileCand) {
+          c_idx[slot] = k;
+          c_x[slot][0] = px;
+          c_x[slot][1] = py;
+          c_x[slot][2] = pz;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  int nc = c_n;
+  if (nc == 0) return;
+  if (nc > kTileCand) {
+    if (threadIdx.x == 0) atomicOr(status, kFlagCand);
+    nc = kTileCand;
+  }
+  // markers of each sphere that can reach the tile in y: the template's
+  // y-component 1 - (2l+1)/N_L is monotone in l, so they form one index range
+  const int nl = G.nl;
+  const double ylo = (j0 - 1.5) * h, yhi = (j0 + TY + 1.0) * h;
+  for (int s = threadIdx.x; s < kTileCand; s += blockDim.x) {
+    int cnt = 0, l0 = 0;
+    if (s < nc) {
+      const double thi = (yhi - c_x[s][1]) / R, tlo = (ylo - c_x[s][1]) / R;
+      l0 = max((int)floor((nl * (1.0 - thi) - 1.0) * 0.5) - 1, 0);
+      const int l1 = min((int)ceil((nl * (1.0 - tlo) - 1.0) * 0.5) + 1, nl - 1);
+      cnt = l1 >= l0 ? l1 - l0 + 1 : 0;
+    }
+    c_l0[s] = l0;
+    c_pref[s] = cnt;
+  }
+  for (int q = threadIdx.x; q < 3 * NODES; q += blockDim.x) acc[q] = (A_t)0;
+  __syncthreads();
+  // exclusive scan of the range lengths (kTileCand entries, one per lane of
+  // the first kTileCand threads; every thread takes part in the barriers)
+  {
+    const int t = threadIdx.x;
+    const bool lane = t < kTileCand;
+    const int v = lane ? c_pref[t] : 0;
+    for (int off = 1; off < kTileCand; off <<= 1) {
+      const int add = (lane && t >= off) ? c_pref[t - off] : 0;
+      __syncthreads();
+      if (lane) c_pref[t] += add;
+      __syncthreads();
+    }
+    const int incl = lane ? c_pref[t] : 0;
+    __syncthreads();
+    if (lane) c_pref[t] = incl - v;
+    if (t == kTileCand - 1) c_pref[kTileCand] = incl;
+    __syncthreads();
+  }
+  const int total = c_pref[kTileCand];
+  const T scale = (T)(G.dV * G.inv_h * G.inv_h * G.inv_h);
+  const size_t M = N * nl;
+  for (int item = threadIdx.x; item < total; item += blockDim.x) {
+    int a = 0, b = kTileCand;   // largest s with c_pref[s] <= item
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (c_pref[mid] <= item) a = mid; else b = mid;
+    }
+    const int s = a;
+    const int l = c_l0[s] + (item - c_pref[s]);
+    const int k = c_idx[s];
+    const double X[3] = {c_x[s][0] + R * templ[3 * l], c_x[s][1] + R * templ[3 * l + 1],
+                         c_x[s][2] + R * templ[3 * l + 2]};
+    // cheap rejection: a marker outside the tile's reach box touches none of
+    // its nodes (conservative; the exact test is the stencil below)
+    if (fabs(min_image(X[0] - mctr[0], G.Lx)) > mhw[0] || fabs(X[1] - mctr[1]) > mhw[1] ||
+        fabs(min_image(X[2] - mctr[2], G.Lz)) > mhw[2])
+      continue;
+    T v[3];
+    if (SRC == 0) {
+      const size_t m = (size_t)k * nl + l;
+      for (int c = 0; c < 3; ++c) v[c] = src[c * M + m];
+    } else {
+      const size_t m = (size_t)perm[k] * nl + l;
+      for (int c = 0; c < 3; ++c) v[c] = src[3 * m + c];
+    }
+    // Per axis only two stencils exist: nodes on cell faces (stagger 0, the
+    // component along that axis) and at cell centres (stagger 1/2, the other
+    // two).  Evaluate each once, with its local tile indices and in-tile mask.
+    T w[3][2][3];
+    int li[3][2][3];
+    unsigned msk[3][2];
+    const int tlen[3] = {TX, TY, TZ}, t0[3] = {i0, j0, k0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        int ic;
+        kernel3<T>(X[a] * G.inv_h - (o ? 0.5 : 0.0), ic, w[a][o]);
+        unsigned m = 0;
+        for (int t = 0; t < 3; ++t) {
+          int node = ic - 1 + t;
+          if (a == 0) node = wrap_once(node, G.nx);
+          if (a == 2) node = wrap_once(node, G.nz);
+          // y rows outside the fluid (and the wall faces of v) take no part
+          const bool row_ok = a != 1 || (node >= (o ? 0 : 1) && node <= G.ny - 1);
+          const int loc = node - t0[a];
+          li[a][o][t] = loc;
+          if (row_ok && loc >= 0 && loc < tlen[a]) m |= 1u << t;
+        }
+        msk[a][o] = m;
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
+      const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
+      if (!(mx && my && mz)) continue;
+      const A_t val = (A_t)(v[c] * scale);
+      A_t *A = acc + c * NODES;
+      for (int kk = 0; kk < 3; ++kk) {
+        if (!(mz >> kk & 1u)) continue;
+        for (int jj = 0; jj < 3; ++jj) {
+          if (!(my >> jj & 1u)) continue;
+          const T wzy = w[2][oz][kk] * w[1][oy][jj];
+          const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * TX;
+          for (int ii = 0; ii < 3; ++ii) {
+            if (!(mx >> ii & 1u)) continue;
+            atomicAdd(&A[base + li[0][ox][ii]], val * (A_t)(wzy * w[0][ox][ii]));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 3 * NODES; q += blockDim.x) {
+    const T add = (T)acc[q];
+    if (acc[q] == (A_t)0) continue;
+    const int c = q / NODES, r = q - c * NODES;
+    const int lz = r / (TX * TY), ly = (r / TX) % TY, lx = r % TX;
+    const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
+    const int nyc = G.ny + (c == 1 ? 1 : 0);
+    if (i >= G.nx || j >= nyc || k >= G.nz) continue;
+    const size_t g = ((size_t)k * nyc + j) * G.nx + i;
+    T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
+    Fp[g] += add;
+  }
 }
 
 template <typename T>
-hipError_t launch_spread_mdf(hipStream_t s, const Geom &G, const Scratch &S, T *f[3], int n,
-                             const T *F0) {
+hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
+                               T *f[3], int n, const T *src_caller) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spread_mdf<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G, S.templ,
-                     S.xs[0], n, (const T *)S.dF, F0, S.perm, f[0], f[1], f[2], S.ft_acc);
+  constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
+  const int ntiles =
+      ((G.nx + TX - 1) / TX) * ((G.ny + 1 + TY - 1) / TY) * ((G.nz + TZ - 1) / TZ);
+  if (src_caller)
+    hipLaunchKernelGGL((k_spread_tiles<T, 1>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
+                       G, C, S.start, S.xs[0], n, S.templ, src_caller, S.perm, f[0], f[1], f[2],
+                       S.status);
+  else
+    hipLaunchKernelGGL((k_spread_tiles<T, 0>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
+                       G, C, S.start, S.xs[0], n, S.templ, (const T *)S.dF, S.perm, f[0], f[1],
+                       f[2], S.status);
   return hipGetLastError();
 }
 
-template hipError_t launch_interp_mdf<float>(hipStream_t, const Geom &, const Scratch &,
-                                             const float *[3], const float *[3], int, double, int,
-                                             int);
-template hipError_t launch_interp_mdf<double>(hipStream_t, const Geom &, const Scratch &,
-                                              const double *[3], const double *[3], int, double,
-                                              int, int);
-template hipError_t launch_spread_mdf<float>(hipStream_t, const Geom &, const Scratch &,
-                                             float *[3], int, const float *);
-template hipError_t launch_spread_mdf<double>(hipStream_t, const Geom &, const Scratch &,
-                                              double *[3], int, const double *);
+template hipError_t launch_spread_tiles<float>(hipStream_t, const Geom &, const Cells &,
+                                               const Scratch &, float *[3], int, const float *);
+template hipError_t launch_spread_tiles<double>(hipStream_t, const Geom &, const Cells &,
+                                                const Scratch &, double *[3], int,
+                                                const double *);
 
 // ---------------------------------------------------------------------------
-// bookkeeping
+// per-sphere force/torque bookkeeping
 // ---------------------------------------------------------------------------
+// acc += part (compensated), for the iterations whose corrections are spread.
+__global__ void k_ft_commit(double *acc, const double *part, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const size_t N = (size_t)n;
+  for (int k = 0; k < 6; ++k) {
+    double S = acc[(2 * k) * N + p], Cc = acc[(2 * k + 1) * N + p];
+    comp_add(S, Cc, part[(2 * k) * N + p], part[(2 * k + 1) * N + p]);
+    acc[(2 * k) * N + p] = S;
+    acc[(2 * k + 1) * N + p] = Cc;
+  }
+}
+
+hipError_t launch_ft_commit(hipStream_t s, const Scratch &S, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ft_commit, dim3((n + 255) / 256), dim3(256), 0, s, S.ft_acc, S.ft_part, n);
+  return hipGetLastError();
+}
+
+// acc = compensated sums of a caller-ordered initial marker force F0.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_marker_sums(Geom G, const double *__restrict__ templ,
+                                                      const T *__restrict__ F0,
+                                                      const int *__restrict__ perm, int n,
+                                                      double *acc) {
+  const int p = xcd_item(blockIdx.x, n);
+  if (p < 0) return;
+  const int l = threadIdx.x;
+  Red red;
+  red_zero(red);
+  if (l < G.nl) {
+    const double rl[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
+    const size_t m = (size_t)perm[p] * G.nl + l;
+    const double d[3] = {(double)F0[3 * m], (double)F0[3 * m + 1], (double)F0[3 * m + 2]};
+    red_set_ft(red, rl, d);
+  }
+  block_reduce(red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) {
+      acc[(2 * k) * (size_t)n + p] = red.s[k];
+      acc[(2 * k + 1) * (size_t)n + p] = red.c[k];
+    }
+}
+
+template <typename T>
+hipError_t launch_marker_sums(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F0) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_marker_sums<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G,
+                     S.templ, F0, S.perm, n, S.ft_acc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_marker_sums<float>(hipStream_t, const Geom &, const Scratch &, int,
+                                              const float *);
+template hipError_t launch_marker_sums<double>(hipStream_t, const Geom &, const Scratch &, int,
+                                               const double *);
+
 __global__ void k_zero_f64(double *p, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x)
@@ -429,45 +679,62 @@ hipError_t launch_ib_begin(hipStream_t s, const Scratch &S, int n) {
   return hipGetLastError();
 }
 
-// Deterministic reduction of the per-sphere slip partials of one iteration
-// into slip_hist[iter] (and the zero-forcing denominator into slot kMaxSlip).
-__global__ __launch_bounds__(1024) void k_slip_reduce(const double *part, int n, double *hist,
-                                                      int iter, int want_den) {
-  __shared__ double lds[2][1024];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    a += part[i];
-    b += part[n + i];
-  }
-  lds[0][threadIdx.x] = a;
-  lds[1][threadIdx.x] = b;
+// Deterministic two-level reduction of the per-sphere slip partials of one
+// pass into slip_hist[slot]: fixed chunks per block, then one block in order.
+constexpr int kSlipBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_slip_partial(const double *part, int n, double *blocks) {
+  __shared__ double lds[256];
+  const int chunk = (n + kSlipBlocks - 1) / kSlipBlocks;
+  const int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, n);
+  double a = 0.0;
+  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) a += part[i];
+  lds[threadIdx.x] = a;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      lds[0][threadIdx.x] += lds[0][threadIdx.x + off];
-      lds[1][threadIdx.x] += lds[1][threadIdx.x + off];
-    }
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    hist[iter] = lds[0][0];
-    if (want_den) hist[PRS_MAX_SLIP + 0] = lds[1][0];
-  }
+  if (threadIdx.x == 0) blocks[blockIdx.x] = lds[0];
 }
 
-hipError_t launch_slip_reduce(hipStream_t s, const Scratch &S, int n, int iter, int want_den) {
-  hipLaunchKernelGGL(k_slip_reduce, dim3(1), dim3(1024), 0, s, S.slip_part, n, S.slip_hist, iter,
-                     want_den);
+__global__ __launch_bounds__(256) void k_slip_final(const double *blocks, double *out) {
+  __shared__ double lds[256];
+  lds[threadIdx.x] = blocks[threadIdx.x];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
+}
+
+// which = 0: the slip of the pass just made -> slip_hist[iter];
+// which = 1: the zero-forcing slip -> slip_hist[PRS_MAX_SLIP].
+hipError_t launch_slip_reduce(hipStream_t s, const Scratch &S, int n, int iter, int which) {
+  if (n == 0) return hipSuccess;
+  const double *part = S.slip_part + (which ? (size_t)n : 0);
+  double *blocks = S.slip_hist + PRS_MAX_SLIP + 1;
+  double *dst = S.slip_hist + (which ? PRS_MAX_SLIP : iter);
+  hipLaunchKernelGGL(k_slip_partial, dim3(kSlipBlocks), dim3(256), 0, s, part, n, blocks);
+  hipLaunchKernelGGL(k_slip_final, dim3(1), dim3(256), 0, s, blocks, dst);
+  return hipGetLastError();
+}
+
+__global__ void k_copy1(const double *src, double *dst) { *dst = *src; }
+
+hipError_t launch_copy_scalar(hipStream_t s, const double *src, double *dst) {
+  hipLaunchKernelGGL(k_copy1, dim3(1), dim3(1), 0, s, src, dst);
   return hipGetLastError();
 }
 
 __global__ void k_ib_finish(const double *acc, int n, double scale, double *fh, double *th) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
+  const size_t N = (size_t)n;
   for (int a = 0; a < 3; ++a) {
-    fh[a * (size_t)n + p] = scale * (acc[(2 * a) * (size_t)n + p] + acc[(2 * a + 1) * (size_t)n + p]);
-    th[a * (size_t)n + p] =
-        scale * (acc[(2 * (a + 3)) * (size_t)n + p] + acc[(2 * (a + 3) + 1) * (size_t)n + p]);
+    fh[a * N + p] = scale * (acc[(2 * a) * N + p] + acc[(2 * a + 1) * N + p]);
+    th[a * N + p] = scale * (acc[(2 * (a + 3)) * N + p] + acc[(2 * (a + 3) + 1) * N + p]);
   }
 }
 

@@ -64,8 +64,9 @@ struct Scratch {
   double *xs[2], *us[2], *ws[2], *x0;
   double *fh, *th;            // [3][n] sorted
   double *ft_acc;             // [12][n]: (sum, compensation) x (Fx Fy Fz Tx Ty Tz)
+  double *ft_part;            // [12][n]: the same for the latest interpolation pass
   double *slip_part;          // [2][n]: slip^2 and zero-forcing slip^2 per sphere
-  double *slip_hist;          // [2][kMaxSlip]
+  double *slip_hist;          // [kMaxSlip + 1 + 256]: per pass, zero-forcing, block partials
   int *ncand, *cand;          // [n], [kCandCap][n]
   // contact history, internal SoA layout [slot][n], double-buffered
   int *h_cnt[2], *h_id[2];
@@ -78,10 +79,11 @@ struct Scratch {
   uint32_t *status;
   unsigned long long *counters;   // [0] directed contacts, [1] pp last, [2] wall last
   double *templ;                  // [nl][3]
+  int *lane_order;                // [nl]: marker handled by interpolation lane i
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_template(hipStream_t s, double *t, int nl);
+hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl);
 
 hipError_t launch_sort(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
                        const double *x_caller, int n, int nkeys_scan_levels);
@@ -93,21 +95,23 @@ hipError_t launch_writeback(hipStream_t s, const Scratch &S, double *x, double *
                             const prs_history *H, double *Fh, double *Th, int n, int buf);
 hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
 
+int brick_edge(double R, double h);
 template <typename T>
-hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const double *templ, const T *gu,
+hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, const T *gu,
                                const T *gv, const T *gw, const double *x, const double *up,
                                const double *om, int n, T *U, T *Ud);
 template <typename T>
-hipError_t launch_spread_plain(hipStream_t s, const Geom &G, const double *templ, const double *x,
-                               int n, const T *F, T *fu, T *fv, T *fw);
-template <typename T>
 hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
-                             const T *f[3], int n, double adt, int iter, int want_den);
+                             const T *f[3], int n, double adt, int den_only);
 template <typename T>
-hipError_t launch_spread_mdf(hipStream_t s, const Geom &G, const Scratch &S, T *f[3], int n,
-                             const T *F0);
+hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
+                               T *f[3], int n, const T *src_caller);
+hipError_t launch_ft_commit(hipStream_t s, const Scratch &S, int n);
+template <typename T>
+hipError_t launch_marker_sums(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F0);
+hipError_t launch_copy_scalar(hipStream_t s, const double *src, double *dst);
 hipError_t launch_ib_begin(hipStream_t s, const Scratch &S, int n);
-hipError_t launch_slip_reduce(hipStream_t s, const Scratch &S, int n, int iter, int want_den);
+hipError_t launch_slip_reduce(hipStream_t s, const Scratch &S, int n, int iter, int which);
 hipError_t launch_ib_finish(hipStream_t s, const Scratch &S, const Geom &G, int n, double rho_f);
 template <typename T>
 hipError_t launch_fill_zero(hipStream_t s, T *p, size_t count);
