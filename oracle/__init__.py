@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "prs_oracle.c")
+_SRCS = [os.path.join(_HERE, "prs_oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SLOTS = 14
@@ -26,7 +26,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-                               "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,6 +70,16 @@ def lib():
         L.or_dem.argtypes = [P, C.c_int32, dp, dp, dp, dp, dp, ip, dp, dp, ip, dp, dp]
         L.or_step.argtypes = [P, dp, dp, dp, dp, dp, dp, C.c_int32, dp, dp, dp, dp, ip, dp, dp, ip,
                               dp, dp, dp, ip]
+        L.or_mlp_nparam.restype = C.c_int
+        L.or_bf16.argtypes = [C.c_double]
+        L.or_bf16.restype = C.c_double
+        L.or_mlp_forward.argtypes = [dp, C.c_int32, dp, dp, C.c_int32]
+        L.or_mlp_forward.restype = None
+        L.or_mlp_loss_grad.argtypes = [dp, C.c_int32, dp, dp, dp, C.c_int32]
+        L.or_mlp_loss_grad.restype = C.c_double
+        L.or_mlp_adam.argtypes = [dp, dp, dp, dp, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                  C.c_double, C.c_double]
+        L.or_mlp_adam.restype = None
         _lib = L
     return _lib
 
@@ -247,3 +257,55 @@ def step(p: Params, uhat, f, x, u, om, hist: History, F0=None):
     it = iters.value
     n_slip = it + 1 if p.tol_mode else max(it, 1)
     return rc, dict(Fh=Fh, Th=Th, slip=slip[:n_slip].copy(), iters=it)
+
+
+# --------------------------------------------------------------------------
+# learned warm start (mlp_oracle.c)
+# --------------------------------------------------------------------------
+MLP_SHAPES = (("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+              ("W3", (16, 64)), ("b3", (16,)))
+
+
+def mlp_nparam() -> int:
+    return lib().or_mlp_nparam()
+
+
+def mlp_pack(d) -> np.ndarray:
+    return np.ascontiguousarray(np.concatenate([np.asarray(d[k], dtype=np.float64).ravel()
+                                                for k, _ in MLP_SHAPES]))
+
+
+def mlp_unpack(flat):
+    out, o = {}, 0
+    for k, s in MLP_SHAPES:
+        n = int(np.prod(s))
+        out[k] = np.asarray(flat[o:o + n]).reshape(s).copy()
+        o += n
+    return out
+
+
+def bf16(x: float) -> float:
+    return lib().or_bf16(float(x))
+
+
+def mlp_forward(params, X, emulate_bf16=True):
+    P = _f64(params)
+    X = _f64(X)
+    Y = np.zeros((X.shape[0], 16))
+    lib().or_mlp_forward(_d(P), X.shape[0], _d(X), _d(Y), int(emulate_bf16))
+    return Y
+
+
+def mlp_loss_grad(params, X, T, emulate_bf16=True):
+    P, X, T = _f64(params), _f64(X), _f64(T)
+    g = np.zeros(mlp_nparam())
+    loss = lib().or_mlp_loss_grad(_d(P), X.shape[0], _d(X), _d(T), _d(g), int(emulate_bf16))
+    return loss, g
+
+
+def mlp_adam(params, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of params, m, v (float64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().or_mlp_adam(_d(params), _d(m), _d(v), _d(g), params.size, int(t), lr, beta1, beta2, eps)
