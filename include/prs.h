@@ -202,6 +202,47 @@ typedef struct prs_timing {
     int64_t n_interp, n_spread, n_substep;
 } prs_timing;
 
+/* ---- learned warm start ------------------------------------------------
+ * Not part of the paper: a small network predicts each marker's initial
+ * forcing, after which the unchanged multi-direct forcing runs, so the plain
+ * method stays both the fallback and the judge.  Network: 16 inputs (12
+ * features zero-padded) -> 64 -> GELU -> 64 -> GELU -> 16 outputs (3 used),
+ * exact-erf GELU, BF16 weights and activations on the matrix cores with FP32
+ * accumulation, FP32 master weights trained by Adam (beta 0.9 / 0.999,
+ * eps 1e-8) on the mean square error of standardised targets.
+ * Parameter vector (FP32, PRS_MLP_PARAMS values, row-major out x in):
+ *   W1[64][16], b1[64], W2[64][64], b2[64], W3[16][64], b3[16].
+ * Normalisation vector (PRS_MLP_NORM values): feature mean[16], feature
+ * std[16], target mean[3], target std[3] (std > 0).
+ * Features of a marker (12, then 4 zeros): slip U_d - I[u-hat] (3), template
+ * normal t_l (3), sphere velocity u_p (3), R omega_p (3).  Target (3): the
+ * marker's total forcing after the plain iterations times alpha dt_f
+ * (velocity units). */
+#define PRS_MLP_PARAMS 6288
+#define PRS_MLP_NORM 38
+typedef struct prs_mlp prs_mlp;
+
+/* Create a network on the current device from HOST arrays; Adam moments start
+ * at zero.  PRS_EINVAL for non-finite values or non-positive std. */
+int prs_mlp_create(const float *params, const float *norm, prs_mlp **out);
+void prs_mlp_destroy(prs_mlp *mlp);
+const char *prs_mlp_last_error(const prs_mlp *mlp);
+/* Copy the FP32 master parameters / normalisation to HOST arrays (nullable). */
+int prs_mlp_get(prs_mlp *mlp, float *params, float *norm);
+/* Y [B][3] for inputs X [B][16] (device, FP32).  raw != 0: X are raw
+ * features, standardised inside, and Y comes back in target units; raw == 0:
+ * X and Y in standardised units.  Asynchronous. */
+int prs_mlp_forward(prs_mlp *mlp, void *stream, const float *X, int32_t B, int raw, float *Y);
+/* Gradient of the loss (1/(3B)) sum (Y - T)^2 for standardised X [B][16] and
+ * T [B][3] (device): grad (device, PRS_MLP_PARAMS FP32, nullable), loss
+ * (HOST, nullable; synchronises when given). */
+int prs_mlp_grad(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
+                 float *grad, double *loss);
+/* One Adam step (gradient of the batch, bias-corrected update of the master
+ * weights and of their BF16 copy) with learning rate lr; loss as above. */
+int prs_mlp_train_step(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
+                       float lr, double *loss);
+
 /* Enable (1) or disable (0) phase timing on this context. */
 int prs_timing_enable(prs_ctx *ctx, int enable);
 /* Copy the accumulated phase times into *out (HOST); reset them if reset != 0. */

@@ -27,7 +27,10 @@ _NAMES = {1: "EINVAL", 2: "ECAPACITY", 3: "EDOMAIN", 4: "ENONFINITE", 5: "EHIP",
 
 EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_interpolate",
            "prs_spread", "prs_contacts", "prs_step_particles", "prs_timing_enable",
-           "prs_timing_read")
+           "prs_timing_read", "prs_mlp_create", "prs_mlp_destroy", "prs_mlp_last_error",
+           "prs_mlp_get", "prs_mlp_forward", "prs_mlp_grad", "prs_mlp_train_step")
+MLP_PARAMS = 6288
+MLP_NORM = 38
 
 
 class PrsError(RuntimeError):
@@ -108,6 +111,16 @@ def lib():
                                          C.POINTER(Stats)]
         L.prs_timing_enable.argtypes = [vp, C.c_int]
         L.prs_timing_read.argtypes = [vp, C.POINTER(Timing), C.c_int]
+        L.prs_mlp_create.argtypes = [vp, vp, C.POINTER(vp)]
+        L.prs_mlp_destroy.argtypes = [vp]
+        L.prs_mlp_destroy.restype = None
+        L.prs_mlp_last_error.argtypes = [vp]
+        L.prs_mlp_last_error.restype = C.c_char_p
+        L.prs_mlp_get.argtypes = [vp, vp, vp]
+        L.prs_mlp_forward.argtypes = [vp, vp, vp, C.c_int32, C.c_int, vp]
+        L.prs_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+        L.prs_mlp_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float,
+                                         C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -315,3 +328,98 @@ class Context:
                                       _ptr(F0), C.byref(st))
         self._err(rc)
         return Fh, Th, st.as_dict()
+
+
+class Mlp:
+    """The learned warm-start network (device weights, Adam state,
+    normalisation), wrapping the prs_mlp_* entry points."""
+
+    def __init__(self, params, norm):
+        import numpy as np
+
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        nv = np.ascontiguousarray(norm, dtype=np.float32).ravel()
+        if p.size != MLP_PARAMS or nv.size != MLP_NORM:
+            raise ValueError("parameter / normalisation vectors of the wrong size")
+        self._h = C.c_void_p()
+        rc = lib().prs_mlp_create(C.c_void_p(p.ctypes.data), C.c_void_p(nv.ctypes.data),
+                                  C.byref(self._h))
+        if rc != PRS_OK:
+            raise PrsError(rc, "prs_mlp_create failed")
+
+    @staticmethod
+    def init_params(seed: int = 0):
+        """Seeded U(+-1/sqrt(fan_in)) weights, zero biases, padding rows and
+        columns zero (flat vector in the library's order)."""
+        import numpy as np
+
+        rng = np.random.default_rng(seed)
+        W1 = rng.uniform(-1, 1, (64, 16)) / np.sqrt(12.0)
+        W1[:, 12:] = 0.0
+        W2 = rng.uniform(-1, 1, (64, 64)) / 8.0
+        W3 = rng.uniform(-1, 1, (16, 64)) / 8.0
+        W3[3:] = 0.0
+        return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(),
+                               np.zeros(16)]).astype(np.float32)
+
+    def close(self):
+        if self._h:
+            lib().prs_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc):
+        if rc != PRS_OK:
+            raise PrsError(rc, lib().prs_mlp_last_error(self._h).decode())
+
+    @staticmethod
+    def _chk(t, shape, name):
+        import torch
+
+        if tuple(t.shape) != tuple(shape) or t.dtype != torch.float32 or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous float32 CUDA tensor of shape {shape}")
+
+    def get(self):
+        import numpy as np
+
+        p = np.zeros(MLP_PARAMS, np.float32)
+        nv = np.zeros(MLP_NORM, np.float32)
+        self._err(lib().prs_mlp_get(self._h, C.c_void_p(p.ctypes.data),
+                                    C.c_void_p(nv.ctypes.data)))
+        return p, nv
+
+    def forward(self, X, raw: bool = True):
+        import torch
+
+        B = X.shape[0]
+        self._chk(X, (B, 16), "X")
+        Y = torch.empty((B, 3), dtype=torch.float32, device=X.device)
+        self._err(lib().prs_mlp_forward(self._h, _stream_ptr(), _ptr(X), B, int(raw), _ptr(Y)))
+        return Y
+
+    def grad(self, X, T):
+        import torch
+
+        B = X.shape[0]
+        self._chk(X, (B, 16), "X")
+        self._chk(T, (B, 3), "T")
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = C.c_double()
+        self._err(lib().prs_mlp_grad(self._h, _stream_ptr(), _ptr(X), _ptr(T), B, _ptr(g),
+                                     C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, X, T, lr: float = 1e-3, want_loss: bool = True):
+        B = X.shape[0]
+        self._chk(X, (B, 16), "X")
+        self._chk(T, (B, 3), "T")
+        loss = C.c_double()
+        self._err(lib().prs_mlp_train_step(self._h, _stream_ptr(), _ptr(X), _ptr(T), B,
+                                           float(lr), C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

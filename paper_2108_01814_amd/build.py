@@ -27,6 +27,7 @@ SOURCES = {
     "prs_ib.hip": [],
     "prs_sort.hip": [],
     "prs_dem.hip": ["-ffp-contract=off"],
+    "prs_mlp.hip": [],
     "prs_capi.hip": [],
 }
 

@@ -1,0 +1,122 @@
+"""Parity of the learned warm-start network on MFMA with the FP64 oracle that
+rounds the same values to BF16 (forward, gradient, Adam), and a training
+sanity check.  The device accumulates in FP32, the oracle in FP64; a BF16
+rounding of an activation can land on the other side of a tie, so element
+maxima get a looser bound than the batch-level quantities."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    import paper_2108_01814_amd as P
+
+    assert torch.cuda.is_available()
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.lib()
+    return oracle
+
+
+def setup(P, seed=3, B=1000):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    params = P.Mlp.init_params(seed)
+    params[1024:1088] = rng.uniform(-0.2, 0.2, 64)        # b1
+    params[5184:5248] = rng.uniform(-0.2, 0.2, 64)        # b2
+    params[6272:6275] = rng.uniform(-0.2, 0.2, 3)         # b3
+    norm = np.concatenate([np.zeros(16), np.ones(16), np.zeros(3), np.ones(3)]).astype(np.float32)
+    X = np.zeros((B, 16), np.float32)
+    X[:, :12] = rng.normal(size=(B, 12))
+    T = rng.normal(size=(B, 3)).astype(np.float32)
+    net = P.Mlp(params, norm)
+    return net, params, norm, X, T, torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda()
+
+
+def test_forward_parity(P, orc):
+    net, params, norm, X, T, Xd, Td = setup(P, B=1003)
+    Y = net.forward(Xd, raw=False).cpu().numpy()
+    ref = orc.mlp_forward(params.astype(np.float64), X.astype(np.float64))[:, :3]
+    err = np.abs(Y - ref)
+    assert np.median(err) / np.abs(ref).max() < 1e-5
+    assert err.max() / np.abs(ref).max() < 2e-2
+
+
+def test_forward_raw_units(P):
+    import torch
+
+    net, params, _, X, T, Xd, Td = setup(P, B=64)
+    mean = np.linspace(-1, 1, 16).astype(np.float32)
+    std = np.linspace(0.5, 2, 16).astype(np.float32)
+    tmean = np.array([0.1, -0.2, 0.3], np.float32)
+    tstd = np.array([2.0, 0.5, 1.5], np.float32)
+    norm = np.concatenate([mean, std, tmean, tstd])
+    net2 = P.Mlp(params, norm)
+    raw = X * std + mean
+    Y_raw = net2.forward(torch.as_tensor(raw).cuda(), raw=True).cpu().numpy()
+    Y_std = net2.forward(Xd, raw=False).cpu().numpy()
+    assert np.allclose(Y_raw, Y_std * tstd + tmean, rtol=1e-3, atol=1e-3)
+
+
+def test_gradient_parity(P, orc):
+    net, params, norm, X, T, Xd, Td = setup(P, B=4000)
+    g, loss = net.grad(Xd, Td)
+    lo, go = orc.mlp_loss_grad(params.astype(np.float64), X.astype(np.float64),
+                               T.astype(np.float64))
+    g = g.cpu().numpy()
+    assert loss == pytest.approx(lo, rel=1e-4)
+    assert np.abs(g - go).max() / np.abs(go).max() < 2e-3
+    assert np.linalg.norm(g - go) / np.linalg.norm(go) < 1e-3
+    # padding rows and columns get exactly zero gradient
+    d = orc.mlp_unpack(g)
+    assert np.all(d["W3"][3:] == 0) and np.all(d["b3"][3:] == 0) and np.all(d["W1"][:, 12:] == 0)
+
+
+def test_adam_step_parity(P, orc):
+    net, params, norm, X, T, Xd, Td = setup(P, B=512)
+    _, go = orc.mlp_loss_grad(params.astype(np.float64), X.astype(np.float64),
+                              T.astype(np.float64))
+    net.train_step(Xd, Td, lr=1e-3)
+    got, _ = net.get()
+    ref = params.astype(np.float64).copy()
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    orc.mlp_adam(ref, m, v, go, 1, lr=1e-3)
+    # the first Adam step moves each weight by lr * g / (|g| + eps) ~ lr sign(g);
+    # compare where the gradient is clearly away from zero (its sign is robust)
+    moved = np.abs(go) > 1e-3 * np.abs(go).max()
+    assert moved.sum() > 3000
+    assert np.abs(got - ref)[moved].max() < 2e-5
+    assert np.array_equal(got[6275:], params[6275:])      # padding outputs untouched
+
+
+def test_training_reduces_loss(P):
+    """A smooth synthetic regression is learned (loss drops by 10x)."""
+    import torch
+
+    rng = np.random.default_rng(11)
+    B = 8192
+    X = np.zeros((B, 16), np.float32)
+    X[:, :12] = rng.normal(size=(B, 12))
+    A = rng.normal(size=(12, 3)) / 4
+    T = (np.tanh(X[:, :12] @ A) * 2).astype(np.float32)
+    T = (T - T.mean(0)) / T.std(0)
+    norm = np.concatenate([np.zeros(16), np.ones(16), np.zeros(3), np.ones(3)]).astype(np.float32)
+    net = P.Mlp(P.Mlp.init_params(1), norm)
+    Xd, Td = torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda()
+    first = net.train_step(Xd, Td, lr=3e-3)
+    for _ in range(300):
+        last = net.train_step(Xd, Td, lr=3e-3, want_loss=False)
+    last = net.train_step(Xd, Td, lr=3e-3)
+    assert last < first / 10
