@@ -108,7 +108,7 @@ typedef struct prs_stats {
     int64_t pairs_last;                /* sphere-sphere pairs at the last substep */
     int64_t wall_last;                 /* sphere-wall contacts at the last substep */
     uint32_t flags;                    /* device status word (0 = clean) */
-    int32_t rejected_learned;          /* reserved: learned warm start rejected */
+    int32_t rejected_learned;          /* 1: the learned warm start was rejected */
 } prs_stats;
 
 /* Create a context.  Checks the parameters, allocates the scratch memory for
@@ -200,6 +200,8 @@ typedef struct prs_timing {
     int64_t steps;
     double ms_zero_f, ms_sort, ms_interp, ms_spread, ms_search, ms_substep, ms_writeback;
     int64_t n_interp, n_spread, n_substep;
+    double ms_learned;     /* the fused feature + network pass of a learned start */
+    int64_t n_learned;
 } prs_timing;
 
 /* ---- learned warm start ------------------------------------------------
@@ -242,6 +244,33 @@ int prs_mlp_grad(prs_mlp *mlp, void *stream, const float *X, const float *T, int
  * weights and of their BF16 copy) with learning rate lr; loss as above. */
 int prs_mlp_train_step(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
                        float lr, double *loss);
+
+/* Attach a network to a context (NULL detaches).  A step on a context with a
+ * network starts the multi-direct forcing from the network's prediction: one
+ * interpolation pass of u-hat computes each marker's features, evaluates the
+ * network on them in the same kernel and writes F0 = prediction /
+ * (alpha dt_f), which is spread before the first iteration.  The prediction
+ * is rejected -- f cleared, the iteration restarted from zero forcing,
+ * stats->rejected_learned = 1 -- when the first relative slip is >= 1 or the
+ * slip grows from one iteration to the next.  Such steps need zero_f = 1 and
+ * F0 = NULL (else PRS_EINVAL) and read the slip back after every iteration.
+ * The context keeps the pointer: the network must outlive its use and must
+ * not be trained concurrently with a step.  PRS_EINVAL when the pass does not
+ * fit the device's LDS. */
+int prs_set_learned(prs_ctx *ctx, const prs_mlp *mlp);
+
+/* Training samples from the plain method: clears f, computes the features of
+ * every marker of the spheres (x, u, om: double [n][3], device) against
+ * u-hat, runs n_iter (1..PRS_MAX_SLIP-1) plain multi-direct-forcing
+ * iterations (f on return: the resulting force field) and writes
+ *   feat  : device float [n][n_markers][16], features (the last 4 zero),
+ *   target: device float [n][n_markers][3], alpha dt_f times the marker's
+ *           total forcing after the n_iter iterations,
+ * both in caller order.  stats (HOST, nullable): iterations and relative
+ * slips as for a step.  Synchronous. */
+int prs_forcing_samples(prs_ctx *ctx, void *stream, const void *const uhat[3], void *const f[3],
+                        const double *x, const double *u, const double *om, int32_t n,
+                        int32_t n_iter, float *feat, float *target, prs_stats *stats);
 
 /* Enable (1) or disable (0) phase timing on this context. */
 int prs_timing_enable(prs_ctx *ctx, int enable);

@@ -309,3 +309,43 @@ def mlp_adam(params, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _f64(g)
     lib().or_mlp_adam(_d(params), _d(m), _d(v), _d(g), params.size, int(t), lr, beta1, beta2, eps)
+
+
+def learned_features(p: Params, uhat, x, up, om):
+    """Features of the learned warm start for every marker, [n, nl, 16] FP64
+    (not part of the paper; the network's input as the library defines it):
+    slip U_d - I[u-hat] with U_d the rigid-body velocity of the marker and
+    I the interpolation of sec. 3.3, the template normal t_l, the sphere
+    velocity u_p and R omega_p; the last four entries zero."""
+    x, up, om = _f64(x), _f64(up), _f64(om)
+    U, Ud = interpolate(p, uhat, x, up, om)
+    t, _ = template(p.nl, p.R, p.h)
+    n = x.shape[0]
+    F = np.zeros((n, p.nl, 16))
+    F[:, :, 0:3] = Ud - U
+    F[:, :, 3:6] = t[None, :, :]
+    F[:, :, 6:9] = up[:, None, :]
+    F[:, :, 9:12] = p.R * om[:, None, :]
+    return F
+
+
+def learned_initial_force(params, norm, feat, adt):
+    """Initial marker force of the learned start, [..., 3]: the network on the
+    standardised features (BF16-emulating forward), de-standardised, divided
+    by alpha dt."""
+    norm = np.asarray(norm, dtype=np.float64)
+    shape = feat.shape[:-1]
+    X = (np.asarray(feat, dtype=np.float64).reshape(-1, 16) - norm[:16]) / norm[16:32]
+    Y = mlp_forward(params, X)[:, :3]
+    return ((Y * norm[35:38] + norm[32:35]) / adt).reshape(*shape, 3)
+
+
+def reject_learned(rel_slip) -> bool:
+    """The fallback rule of the learned start: reject when the first relative
+    slip is not below one or the slip grows from one pass to the next."""
+    s = list(rel_slip)
+    if not s:
+        return False
+    if not s[0] < 1.0:
+        return True
+    return any(b > a for a, b in zip(s, s[1:]))

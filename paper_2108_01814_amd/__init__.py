@@ -28,7 +28,8 @@ _NAMES = {1: "EINVAL", 2: "ECAPACITY", 3: "EDOMAIN", 4: "ENONFINITE", 5: "EHIP",
 EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_interpolate",
            "prs_spread", "prs_contacts", "prs_step_particles", "prs_timing_enable",
            "prs_timing_read", "prs_mlp_create", "prs_mlp_destroy", "prs_mlp_last_error",
-           "prs_mlp_get", "prs_mlp_forward", "prs_mlp_grad", "prs_mlp_train_step")
+           "prs_mlp_get", "prs_mlp_forward", "prs_mlp_grad", "prs_mlp_train_step",
+           "prs_set_learned", "prs_forcing_samples")
 MLP_PARAMS = 6288
 MLP_NORM = 38
 
@@ -72,14 +73,16 @@ class Stats(C.Structure):
     def as_dict(self):
         return dict(iterations=self.iterations, rel_slip=list(self.rel_slip[: self.n_slip]),
                     contacts=self.contacts, pairs_last=self.pairs_last,
-                    wall_last=self.wall_last, flags=self.flags)
+                    wall_last=self.wall_last, flags=self.flags,
+                    rejected_learned=self.rejected_learned)
 
 
 class Timing(C.Structure):
     _fields_ = [("steps", C.c_int64), ("ms_zero_f", C.c_double), ("ms_sort", C.c_double),
                 ("ms_interp", C.c_double), ("ms_spread", C.c_double), ("ms_search", C.c_double),
                 ("ms_substep", C.c_double), ("ms_writeback", C.c_double),
-                ("n_interp", C.c_int64), ("n_spread", C.c_int64), ("n_substep", C.c_int64)]
+                ("n_interp", C.c_int64), ("n_spread", C.c_int64), ("n_substep", C.c_int64),
+                ("ms_learned", C.c_double), ("n_learned", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +114,9 @@ def lib():
                                          C.POINTER(Stats)]
         L.prs_timing_enable.argtypes = [vp, C.c_int]
         L.prs_timing_read.argtypes = [vp, C.POINTER(Timing), C.c_int]
+        L.prs_set_learned.argtypes = [vp, vp]
+        L.prs_forcing_samples.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp,
+                                          C.c_int32, C.c_int32, vp, vp, C.POINTER(Stats)]
         L.prs_mlp_create.argtypes = [vp, vp, C.POINTER(vp)]
         L.prs_mlp_destroy.argtypes = [vp]
         L.prs_mlp_destroy.restype = None
@@ -328,6 +334,38 @@ class Context:
                                       _ptr(F0), C.byref(st))
         self._err(rc)
         return Fh, Th, st.as_dict()
+
+
+    def set_learned(self, mlp: Optional["Mlp"]):
+        """Start every following step from the network's prediction (None:
+        plain start).  The context keeps a reference to the network."""
+        self._err(lib().prs_set_learned(self._h, mlp._h if mlp is not None else None))
+        self._mlp = mlp
+
+    def forcing_samples(self, uhat, f, x, u, om, n_iter: int, feat=None, target=None):
+        """Features [n, n_markers, 16] and targets [n, n_markers, 3] (float32,
+        caller order) from n_iter plain forcing iterations; f is overwritten
+        with the resulting force field.  Returns (feat, target, stats)."""
+        import torch
+
+        n = x.shape[0]
+        nl = self.p.n_markers
+        self._chk_fields(uhat, "uhat")
+        self._chk_fields(f, "f")
+        self._chk_particles(n, x=x, u=u, om=om)
+        if feat is None:
+            feat = torch.empty((n, nl, 16), dtype=torch.float32, device=self.device)
+        if target is None:
+            target = torch.empty((n, nl, 3), dtype=torch.float32, device=self.device)
+        self._chk(feat, (n, nl, 16), torch.float32, "feat")
+        self._chk(target, (n, nl, 3), torch.float32, "target")
+        uh = (C.c_void_p * 3)(*[t.data_ptr() for t in uhat])
+        ff = (C.c_void_p * 3)(*[t.data_ptr() for t in f])
+        st = Stats()
+        self._err(lib().prs_forcing_samples(self._h, _stream_ptr(), uh, ff, _ptr(x), _ptr(u),
+                                            _ptr(om), n, int(n_iter), _ptr(feat), _ptr(target),
+                                            C.byref(st)))
+        return feat, target, st.as_dict()
 
 
 class Mlp:

@@ -1,6 +1,7 @@
 // extern "C" boundary of the library: argument validation, context and
 // scratch management, and the host-side sequencing of the kernels on the
 // caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,8 +33,9 @@ struct prs_ctx {
   };
   std::vector<Mark> marks;
   hipEvent_t open_ev = nullptr;
-  double ms[7] = {0, 0, 0, 0, 0, 0, 0};
-  int64_t launches[7] = {0, 0, 0, 0, 0, 0, 0};
+  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const prs_mlp *mlp = nullptr;   // learned warm start (prs_set_learned)
   int64_t steps = 0;
 };
 
@@ -121,7 +123,8 @@ int check_n(prs_ctx *c, int32_t n) {
   return PRS_OK;
 }
 
-enum Phase { kZeroF = 0, kSort, kInterp, kSpread, kSearch, kSubstep, kWriteback };
+enum Phase { kZeroF = 0, kSort, kInterp, kSpread, kSearch, kSubstep, kWriteback, kLearned };
+constexpr int kPhases = 8;
 
 hipError_t next_event(prs_ctx *c, hipEvent_t *ev) {
   if (c->events_used == c->events.size()) {
@@ -166,13 +169,24 @@ hipError_t phase_collect(prs_ctx *c) {
   return hipSuccess;
 }
 
+template <typename T>
+int clear_field(prs_ctx *c, hipStream_t s, void *const f[3]) {
+  for (int k = 0; k < 3; ++k) HIP_TRY(c, launch_fill_zero<T>(s, (T *)f[k], grid_count(c, k)));
+  return PRS_OK;
+}
+
 // Multi-direct forcing on the sorted spheres (Jacobi): every iteration
 // interpolates u** = u-hat + alpha dt f at all markers, then spreads the
 // corrections into f.  In tolerance mode the relative slip of each pass is
 // read back and the loop stops before spreading once it is below tol.
+//   F0      : caller-ordered initial marker force, spread first (or NULL);
+//   learned : start from the attached network's prediction (f is zero);
+//   target  : when set, alpha dt times every correction is accumulated into
+//             it (training samples).
 template <typename T>
 int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *const f[3], int n,
-                const void *F0, bool need_den, int &iters, int &n_slip) {
+                const void *F0, bool need_den, bool learned, int n_fixed, float *target,
+                int &iters, int &n_slip, int &rejected) {
   Scratch &S = c->S;
   const prs_params &q = c->p;
   const double adt = q.alpha * q.dt_f;
@@ -180,38 +194,74 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
   T *ff[3] = {(T *)f[0], (T *)f[1], (T *)f[2]};
   const T *fc[3] = {ff[0], ff[1], ff[2]};
   double *hist_host = c->host_pinned;
-  if (need_den) {
+  bool den_ready = false;
+  if (learned) {
+    // features, zero-forcing slip and the prediction F0 -> dF in one pass
+    LearnArgs la{};
+    mlp_buffers(c->mlp, &la);
     HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 1));
-    HIP_TRY(c, phase_end(c, s, kInterp));
+    HIP_TRY(c, launch_interp_learned<T>(s, c->G, S, uh, n, adt, la));
+    HIP_TRY(c, phase_end(c, s, kLearned));
     HIP_TRY(c, launch_slip_reduce(s, S, n, 0, 1));
-  }
-  if (F0) {
-    HIP_TRY(c, launch_marker_sums<T>(s, c->G, S, n, (const T *)F0));
-    HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0));
-    HIP_TRY(c, phase_end(c, s, kSpread));
-  } else {
     HIP_TRY(c, launch_ib_begin(s, S, n));
+    HIP_TRY(c, launch_ft_commit(s, S, n));
+    HIP_TRY(c, phase_begin(c, s));
+    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr));
+    HIP_TRY(c, phase_end(c, s, kSpread));
+    den_ready = true;
+  } else {
+    if (need_den) {
+      HIP_TRY(c, phase_begin(c, s));
+      HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 1));
+      HIP_TRY(c, phase_end(c, s, kInterp));
+      HIP_TRY(c, launch_slip_reduce(s, S, n, 0, 1));
+      den_ready = true;
+    }
+    if (F0) {
+      HIP_TRY(c, launch_marker_sums<T>(s, c->G, S, n, (const T *)F0));
+      HIP_TRY(c, phase_begin(c, s));
+      HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0));
+      HIP_TRY(c, phase_end(c, s, kSpread));
+    } else {
+      HIP_TRY(c, launch_ib_begin(s, S, n));
+    }
   }
-  const int limit = q.tol_mode ? q.max_iter : q.n_iter;
+  const bool tol_mode = q.tol_mode && n_fixed < 0;
+  const int n_iter = n_fixed >= 0 ? n_fixed : q.n_iter;
+  const int limit = q.max_iter;
   for (int it = 0;; ++it) {
-    if (!q.tol_mode && it >= q.n_iter) break;
+    if (!tol_mode && it >= n_iter) break;
     HIP_TRY(c, phase_begin(c, s));
     HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 0));
     HIP_TRY(c, phase_end(c, s, kInterp));
     HIP_TRY(c, launch_slip_reduce(s, S, n, it, 0));
-    if (it == 0 && !need_den)
+    if (it == 0 && !den_ready) {
+      // f = 0 and no initial force: this pass saw u** = u-hat
       HIP_TRY(c, launch_copy_scalar(s, S.slip_hist, S.slip_hist + PRS_MAX_SLIP));
+      den_ready = true;
+    }
     n_slip = it + 1;
-    if (q.tol_mode) {
+    if (tol_mode || learned) {
       HIP_TRY(c, hipMemcpyAsync(hist_host, S.slip_hist, sizeof(double) * (PRS_MAX_SLIP + 1),
                                 hipMemcpyDeviceToHost, s));
       HIP_TRY(c, hipStreamSynchronize(s));
       const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
       const double rel = den > 0 ? std::sqrt(hist_host[it]) / den : 0.0;
-      if (rel < q.tol || it >= limit) break;
+      if (learned && ((it == 0 && !(rel < 1.0)) || (it > 0 && hist_host[it] > hist_host[it - 1]))) {
+        // the prediction made things worse: restart from zero forcing
+        rejected = 1;
+        learned = false;
+        HIP_TRY(c, phase_begin(c, s));
+        if (int rc = clear_field<T>(c, s, f)) return rc;
+        HIP_TRY(c, phase_end(c, s, kZeroF));
+        HIP_TRY(c, launch_ib_begin(s, S, n));
+        iters = 0;
+        it = -1;
+        continue;
+      }
+      if (tol_mode && (rel < q.tol || it >= limit)) break;
     }
+    if (target) HIP_TRY(c, launch_accum_target<T>(s, c->G, S, n, adt, target));
     HIP_TRY(c, launch_ft_commit(s, S, n));
     HIP_TRY(c, phase_begin(c, s));
     HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr));
@@ -219,6 +269,15 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
     iters = it + 1;
   }
   return PRS_OK;
+}
+
+void fill_stats(prs_stats *stats, const double *hist_host, int iters, int n_slip) {
+  memset(stats, 0, sizeof *stats);
+  stats->iterations = iters;
+  stats->n_slip = n_slip;
+  const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
+  for (int k = 0; k < n_slip; ++k)
+    stats->rel_slip[k] = den > 0 ? std::sqrt(hist_host[k]) / den : 0.0;
 }
 
 }  // namespace
@@ -428,7 +487,7 @@ int prs_spread(prs_ctx *c, void *stream, const double *x, int32_t n, const void 
   }
   if (n == 0) return PRS_OK;
   HIP_TRY(c, launch_sort(s, S, c->C_step, c->G, x, n, 0));
-  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n));
+  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n, nullptr, nullptr));
   if (c->p.precision == PRS_F64)
     HIP_TRY(c, launch_spread_tiles<double>(s, c->G, c->C_step, S, (double **)g, n,
                                            (const double *)F));
@@ -450,7 +509,7 @@ int prs_contacts(prs_ctx *c, void *stream, const double *x, int32_t n, int32_t *
   Scratch &S = c->S;
   HIP_TRY(c, launch_reset_status(s, S));
   HIP_TRY(c, launch_sort(s, S, c->C_touch, c->G, x, n, 0));
-  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n));
+  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n, nullptr, nullptr));
   HIP_TRY(c, launch_contact_list(s, S, c->C_touch, c->G, n, pairs, cap, 0));
   if (n > 0) HIP_TRY(c, launch_scan(s, S.ccount, n, S.scan_tmp));
   HIP_TRY(c, launch_contact_list(s, S, c->C_touch, c->G, n, pairs, cap, 1));
@@ -478,10 +537,11 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
   if (n > 0 && (!x || !u || !om || !Fh || !Th || !H || !H->partner || !H->delta_t || !H->u_in ||
                 !H->count))
     return fail(c, PRS_EINVAL, "step: null particle array");
+  if (c->mlp && (!zero_f || F0))
+    return fail(c, PRS_EINVAL, "step: a learned start needs zero_f = 1 and no F0");
   hipStream_t s = as_stream(stream);
   Scratch &S = c->S;
   const prs_params &q = c->p;
-  const double adt = q.alpha * q.dt_f;
   const bool f64 = q.precision == PRS_F64;
 
   HIP_TRY(c, launch_reset_status(s, S));
@@ -505,15 +565,19 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
   }
 
   // ---- immersed-boundary forcing (multi-direct forcing, Jacobi) ----
-  int iters = 0, n_slip = 0;
+  int iters = 0, n_slip = 0, rejected = 0;
   double *hist_host = c->host_pinned;   // [0..63] slip^2, [64] zero-forcing slip^2
   if (n > 0) {
     // the first pass sees f = 0 only when the field was cleared here and no
     // initial marker force is spread; otherwise the zero-forcing slip needs a
     // pass of its own
     const bool need_den = !zero_f || F0 != nullptr;
-    const int rc = f64 ? run_forcing<double>(c, s, uhat, f, n, F0, need_den, iters, n_slip)
-                       : run_forcing<float>(c, s, uhat, f, n, F0, need_den, iters, n_slip);
+    const bool learned = c->mlp != nullptr;
+    const int rc =
+        f64 ? run_forcing<double>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
+                                  n_slip, rejected)
+            : run_forcing<float>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
+                                 n_slip, rejected);
     if (rc != PRS_OK) return rc;
     HIP_TRY(c, launch_ib_finish(s, S, c->G, n, q.rho_f));
 
@@ -541,18 +605,87 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
   HIP_TRY(c, hipStreamSynchronize(s));
   HIP_TRY(c, phase_collect(c));
   if (stats) {
-    memset(stats, 0, sizeof *stats);
-    stats->iterations = iters;
-    stats->n_slip = n_slip;
-    const double den = std::sqrt(hist_host[PRS_MAX_SLIP]);
-    for (int k = 0; k < n_slip; ++k)
-      stats->rel_slip[k] = den > 0 ? std::sqrt(hist_host[k]) / den : 0.0;
+    fill_stats(stats, hist_host, iters, n_slip);
+    stats->rejected_learned = rejected;
     stats->contacts = (int64_t)cnt[0];
     stats->pairs_last = (int64_t)cnt[1] / 2;
     stats->wall_last = (int64_t)cnt[2];
     stats->flags = st;
   }
   if (int code = status_code(st)) return fail(c, code, "step: %s", status_text(st));
+  return PRS_OK;
+}
+
+int prs_set_learned(prs_ctx *c, const prs_mlp *mlp) {
+  if (!c) return PRS_EINVAL;
+  if (mlp) {
+    const int nb = brick_edge(c->p.radius, c->p.h);
+    const size_t brick = (size_t)nb * nb * nb * (c->p.precision == PRS_F64 ? 8 : 4);
+    const size_t need = std::max(brick, learned_lds_bytes(c->p.n_markers)) + 4096;
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    if (need > prop.sharedMemPerBlock)
+      return fail(c, PRS_EINVAL, "set_learned: %zu bytes of LDS needed, %zu available", need,
+                  (size_t)prop.sharedMemPerBlock);
+  }
+  c->mlp = mlp;
+  return PRS_OK;
+}
+
+int prs_forcing_samples(prs_ctx *c, void *stream, const void *const uhat[3], void *const f[3],
+                        const double *x, const double *u, const double *om, int32_t n,
+                        int32_t n_iter, float *feat, float *target, prs_stats *stats) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!uhat || !f || !uhat[0] || !uhat[1] || !uhat[2] || !f[0] || !f[1] || !f[2])
+    return fail(c, PRS_EINVAL, "samples: null field");
+  if (n_iter < 1 || n_iter > PRS_MAX_SLIP - 1)
+    return fail(c, PRS_EINVAL, "samples: n_iter = %d outside 1..%d", n_iter, PRS_MAX_SLIP - 1);
+  if (n > 0 && (!x || !u || !om || !feat || !target))
+    return fail(c, PRS_EINVAL, "samples: null particle or output array");
+  hipStream_t s = as_stream(stream);
+  Scratch &S = c->S;
+  const bool f64 = c->p.precision == PRS_F64;
+  HIP_TRY(c, launch_reset_status(s, S));
+  c->marks.clear();
+  c->events_used = 0;
+  int rc = f64 ? clear_field<double>(c, s, f) : clear_field<float>(c, s, f);
+  if (rc) return rc;
+  int iters = 0, n_slip = 0, rejected = 0;
+  if (n > 0) {
+    HIP_TRY(c, launch_sort(s, S, c->C_step, c->G, x, n, 0));
+    HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n, u, om));
+    const size_t M = (size_t)n * c->p.n_markers;
+    HIP_TRY(c, launch_fill_zero<float>(s, target, 3 * M));
+    if (f64) {
+      const double *uh[3] = {(const double *)uhat[0], (const double *)uhat[1],
+                             (const double *)uhat[2]};
+      HIP_TRY(c, launch_interp_feat<double>(s, c->G, S, uh, n, feat));
+    } else {
+      const float *uh[3] = {(const float *)uhat[0], (const float *)uhat[1],
+                            (const float *)uhat[2]};
+      HIP_TRY(c, launch_interp_feat<float>(s, c->G, S, uh, n, feat));
+    }
+    // f = 0: the first iteration's slip is the zero-forcing slip
+    rc = f64 ? run_forcing<double>(c, s, uhat, f, n, nullptr, false, false, n_iter, target, iters,
+                                   n_slip, rejected)
+             : run_forcing<float>(c, s, uhat, f, n, nullptr, false, false, n_iter, target, iters,
+                                  n_slip, rejected);
+    if (rc) return rc;
+  }
+  uint32_t st = 0;
+  double *hist_host = c->host_pinned;
+  HIP_TRY(c, hipMemcpyAsync(&st, S.status, sizeof st, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(hist_host, S.slip_hist, sizeof(double) * (PRS_MAX_SLIP + 1),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->marks.clear();
+  c->events_used = 0;
+  if (stats) {
+    fill_stats(stats, hist_host, iters, n_slip);
+    stats->flags = st;
+  }
+  if (int code = status_code(st)) return fail(c, code, "samples: %s", status_text(st));
   return PRS_OK;
 }
 
@@ -577,8 +710,10 @@ int prs_timing_read(prs_ctx *c, prs_timing *out, int reset) {
   out->n_interp = c->launches[kInterp];
   out->n_spread = c->launches[kSpread];
   out->n_substep = c->launches[kSubstep];
+  out->ms_learned = c->ms[kLearned];
+  out->n_learned = c->launches[kLearned];
   if (reset) {
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < kPhases; ++k) {
       c->ms[k] = 0.0;
       c->launches[k] = 0;
     }

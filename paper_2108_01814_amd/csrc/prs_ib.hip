@@ -17,8 +17,10 @@
 // adds the tile to the force field
 // with plain coalesced read-modify-writes.  Every grid node belongs to exactly
 // one tile, so no global atomics are needed.
+#include <algorithm>
 #include <type_traits>
 
+#include "prs_mlp.h"
 #include "prs_stencil.h"
 
 namespace prs {
@@ -67,10 +69,23 @@ int brick_edge(double R, double h) { return (int)std::ceil(2.0 * R / h) + 5; }
 
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
+size_t learned_lds_bytes(int nl) {
+  return kMlpLdsBytes + (size_t)block_for(nl) * (kMlpIn * sizeof(unsigned short) +
+                                                 kMlpUsed * sizeof(float));
+}
+
 // ---------------------------------------------------------------------------
 // interpolation with an LDS brick per sphere
 // ---------------------------------------------------------------------------
-enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2 };
+enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2, kInterpFeat = 3, kInterpLearned = 4 };
+
+// MODE kInterpFeat   : like kInterpDen, and writes each marker's raw features
+//                      (slip, normal, u_p, R omega_p, zero padding) to feat.
+// MODE kInterpLearned: like kInterpDen, then evaluates the warm-start network
+//                      on the features and writes the initial marker force
+//                      F0 = prediction / (alpha dt) [3][M] and its per-sphere
+//                      force/torque sums.
+
 
 // MODE kInterpMDF  : sorted SoA state; u** = a + adt*b; writes dF [3][M],
 //                    the slip partial and the force/torque partials.
@@ -103,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     const T *__restrict__ b2, double adt, const double *__restrict__ xs,
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
-    double *__restrict__ ft_part, const int *__restrict__ order) {
+    double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la) {
   extern __shared__ unsigned char smem_raw[];
   T *brick = reinterpret_cast<T *>(smem_raw);
   if (NB > 0) nb = NB;
@@ -225,6 +240,61 @@ __global__ __launch_bounds__(1024) void k_interp(
   }
   Red red;
   red_zero(red);
+  // features of the learned warm start: slip, normal, u_p, R omega_p
+  double featd[kMlpFeat];
+  if (MODE == kInterpFeat || MODE == kInterpLearned) {
+    for (int c = 0; c < 3; ++c) {
+      featd[c] = Ud[c] - (double)U[c];
+      featd[3 + c] = active ? templ[3 * l + c] : 0.0;
+      featd[6 + c] = up[c];
+      featd[9 + c] = G.R * wp[c];
+    }
+  }
+  if (MODE == kInterpFeat && active) {
+    float *dst = la.feat + ((size_t)la.perm[p] * G.nl + l) * kMlpIn;
+    for (int k = 0; k < kMlpFeat; ++k) dst[k] = (float)featd[k];
+    for (int k = kMlpFeat; k < kMlpIn; ++k) dst[k] = 0.f;
+  }
+  if constexpr (MODE == kInterpLearned) {
+    // the network on the matrix cores: each wave evaluates its 64 markers as
+    // four 16-marker tiles; features and predictions pass through LDS
+    // the brick's LDS is reused: weights, then standardised inputs (BF16),
+    // then predictions (FP32)
+    MlpLds &L = *reinterpret_cast<MlpLds *>(smem_raw);
+    unsigned short *fl = reinterpret_cast<unsigned short *>(smem_raw + kMlpLdsBytes);
+    float *yl = reinterpret_cast<float *>(fl + blockDim.x * kMlpIn);
+    __syncthreads();   // the brick is no longer read
+    mlp_stage(L, la.wbf, la.master, false);
+    for (int k = 0; k < kMlpIn; ++k) {
+      float v = 0.f;
+      if (active && k < kMlpFeat)
+        v = (float)((featd[k] - (double)la.norm[k]) / (double)la.norm[kMlpIn + k]);
+      fl[threadIdx.x * kMlpIn + k] = to_bf16(v);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, r = threadIdx.x & 15, q = (threadIdx.x >> 4) & 3;
+    for (int t = 0; t < 4; ++t) {
+      const int slot = 64 * wave + 16 * t + r;
+      MlpFwd s;
+      mlp_forward_tile(L, lds4(&fl[slot * kMlpIn + 4 * q]), s);
+      if (q == 0)
+        for (int i = 0; i < kMlpUsed; ++i) yl[slot * kMlpUsed + i] = s.y[i];
+    }
+    __syncthreads();
+    if (active) {
+      // de-standardise in FP64: F0 = (y std + mean) / (alpha dt)
+      const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        const double y = (double)yl[threadIdx.x * kMlpUsed + c];
+        const T f0 = (T)((y * (double)la.norm[2 * kMlpIn + kMlpUsed + c] +
+                          (double)la.norm[2 * kMlpIn + c]) / adt);
+        out[c * M + m] = f0;
+        d[c] = (double)f0;
+      }
+      red_set_ft(red, rl, d);
+    }
+  }
   if (active) {
     if (MODE == kInterpMDF) {
       const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
@@ -246,15 +316,14 @@ __global__ __launch_bounds__(1024) void k_interp(
   }
   block_reduce(red);
   if (threadIdx.x == 0) {
-    if (MODE == kInterpMDF) {
-      slip_part[p] = red.q[0];
+    if (MODE == kInterpMDF || MODE == kInterpLearned) {
+      if (MODE == kInterpMDF) slip_part[p] = red.q[0];
       for (int k = 0; k < 6; ++k) {
         ft_part[(2 * k) * N + p] = red.s[k];
         ft_part[(2 * k + 1) * N + p] = red.c[k];
       }
-    } else {
-      slip_part[N + p] = red.q[1];
     }
+    if (MODE != kInterpMDF) slip_part[N + p] = red.q[1];
   }
 }
 
@@ -265,16 +334,16 @@ void launch_interp_nb(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Ge
                       const double *templ, const T *a0, const T *a1, const T *a2, const T *b0,
                       const T *b1, const T *b2, double adt, const double *xs, const double *us,
                       const double *ws, int n, int nb, T *out, T *out2, double *slip_part,
-                      double *ft_part, const int *order) {
+                      double *ft_part, const int *order, const LearnArgs &la) {
   if (nb == 15)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 15>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
   else if (nb == 21)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 21>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
   else
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 0>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
 }
 
 template <typename T, int MODE>
@@ -282,18 +351,20 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
                              const T *a1, const T *a2, const T *b0, const T *b1, const T *b2,
                              double adt, const double *xs, const double *us, const double *ws,
                              int n, T *out, T *out2, double *slip_part, double *ft_part,
-                             const int *order) {
+                             const int *order, const LearnArgs &la = LearnArgs{}) {
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
   const size_t one = sizeof(T) * nb * nb * nb;
   const bool all3 = 3 * one <= PRS_BRICK_ALL3_MAX_BYTES;
   const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
+  size_t lds = all3 ? 3 * one : one;
+  if (MODE == kInterpLearned) lds = std::max(lds, learned_lds_bytes(G.nl));
   if (all3)
-    launch_interp_nb<T, MODE, true>(grid, block, 3 * one, s, G, templ, a0, a1, a2, b0, b1, b2,
-                                    adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+    launch_interp_nb<T, MODE, true>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
+                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
   else
-    launch_interp_nb<T, MODE, false>(grid, block, one, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order);
+    launch_interp_nb<T, MODE, false>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
+                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
   return hipGetLastError();
 }
 
@@ -318,6 +389,48 @@ hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, con
                                           S.slip_part, S.ft_part, S.lane_order);
 }
 
+template <typename T>
+hipError_t launch_interp_feat(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3], int n,
+                              float *feat) {
+  LearnArgs la{};
+  la.perm = S.perm;
+  la.feat = feat;
+  return launch_interp_any<T, kInterpFeat>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+                                           nullptr, 0.0, S.xs[0], S.us[0], S.ws[0], n, nullptr,
+                                           nullptr, S.slip_part, nullptr, S.lane_order, la);
+}
+
+template <typename T>
+hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
+                                 int n, double adt, const LearnArgs &la) {
+  return launch_interp_any<T, kInterpLearned>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+                                              nullptr, adt, S.xs[0], S.us[0], S.ws[0], n,
+                                              (T *)S.dF, nullptr, S.slip_part, S.ft_part,
+                                              S.lane_order, la);
+}
+
+// target[caller marker][c] += adt * dF[c][sorted marker]
+template <typename T>
+__global__ void k_accum_target(const T *__restrict__ dF, const int *__restrict__ perm, int n,
+                               int nl, double adt, float *__restrict__ target) {
+  const size_t M = (size_t)n * nl;
+  const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int p = (int)(m / nl), l = (int)(m - (size_t)p * nl);
+  const size_t dst = ((size_t)perm[p] * nl + l) * 3;
+  for (int c = 0; c < 3; ++c) target[dst + c] += (float)(adt * (double)dF[c * M + m]);
+}
+
+template <typename T>
+hipError_t launch_accum_target(hipStream_t s, const Geom &G, const Scratch &S, int n, double adt,
+                               float *target) {
+  const size_t M = (size_t)n * G.nl;
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_accum_target<T>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s,
+                     (const T *)S.dF, S.perm, n, G.nl, adt, target);
+  return hipGetLastError();
+}
+
 template hipError_t launch_interp_plain<float>(hipStream_t, const Geom &, const Scratch &,
                                                const float *, const float *, const float *,
                                                const double *, const double *, const double *,
@@ -331,6 +444,20 @@ template hipError_t launch_interp_mdf<float>(hipStream_t, const Geom &, const Sc
 template hipError_t launch_interp_mdf<double>(hipStream_t, const Geom &, const Scratch &,
                                               const double *[3], const double *[3], int, double,
                                               int);
+template hipError_t launch_interp_feat<float>(hipStream_t, const Geom &, const Scratch &,
+                                              const float *[3], int, float *);
+template hipError_t launch_interp_feat<double>(hipStream_t, const Geom &, const Scratch &,
+                                               const double *[3], int, float *);
+template hipError_t launch_interp_learned<float>(hipStream_t, const Geom &, const Scratch &,
+                                                 const float *[3], int, double,
+                                                 const LearnArgs &);
+template hipError_t launch_interp_learned<double>(hipStream_t, const Geom &, const Scratch &,
+                                                  const double *[3], int, double,
+                                                  const LearnArgs &);
+template hipError_t launch_accum_target<float>(hipStream_t, const Geom &, const Scratch &, int,
+                                               double, float *);
+template hipError_t launch_accum_target<double>(hipStream_t, const Geom &, const Scratch &, int,
+                                                double, float *);
 
 // ---------------------------------------------------------------------------
 // spreading by grid tiles

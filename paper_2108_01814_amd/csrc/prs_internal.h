@@ -82,6 +82,16 @@ struct Scratch {
   int *lane_order;                // [nl]: marker handled by interpolation lane i
 };
 
+// Learned warm start: the network's device buffers and, for the feature
+// pass, the output array and the sorted-to-caller permutation.
+struct LearnArgs {
+  const unsigned short *wbf;   // BF16 weights
+  const float *master;         // FP32 master weights (biases)
+  const float *norm;           // feature mean/std, target mean/std
+  float *feat;                 // feature pass: [n][nl][16] in caller order
+  const int *perm;             // sorted position -> caller index
+};
+
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl);
 
@@ -90,7 +100,7 @@ hipError_t launch_sort(hipStream_t s, const Scratch &S, const Cells &C, const Ge
 hipError_t launch_gather_state(hipStream_t s, const Scratch &S, const Geom &G, const double *x,
                                const double *u, const double *om, const prs_history *H, int n);
 hipError_t launch_gather_pos(hipStream_t s, const Scratch &S, const Geom &G, const double *x,
-                             int n);
+                             int n, const double *u, const double *om);
 hipError_t launch_writeback(hipStream_t s, const Scratch &S, double *x, double *u, double *om,
                             const prs_history *H, double *Fh, double *Th, int n, int buf);
 hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
@@ -103,6 +113,20 @@ hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, c
 template <typename T>
 hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
                              const T *f[3], int n, double adt, int den_only);
+template <typename T>
+hipError_t launch_interp_feat(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3], int n,
+                              float *feat);
+template <typename T>
+hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
+                                 int n, double adt, const LearnArgs &la);
+template <typename T>
+hipError_t launch_accum_target(hipStream_t s, const Geom &G, const Scratch &S, int n, double adt,
+                               float *target);
+// Dynamic LDS the learned pass needs besides the grid brick.
+size_t learned_lds_bytes(int nl);
+// Device buffers of a network (defined with the network).
+void mlp_buffers(const prs_mlp *mlp, LearnArgs *la);
+
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
                                T *f[3], int n, const T *src_caller);

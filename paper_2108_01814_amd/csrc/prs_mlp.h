@@ -75,6 +75,8 @@ struct MlpLds {
   float b1[kMlpHid], b2[kMlpHid], b3[kMlpOut];
 };
 
+constexpr size_t kMlpLdsBytes = (sizeof(MlpLds) + 15) & ~(size_t)15;
+
 // Whole workgroup: copy the BF16 weights and FP32 biases into LDS.
 __device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ wbf,
                                  const float *__restrict__ master, bool transposed) {

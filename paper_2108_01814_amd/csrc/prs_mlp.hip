@@ -231,6 +231,12 @@ struct prs_mlp {
   std::string err;
 };
 
+void prs::mlp_buffers(const prs_mlp *mlp, prs::LearnArgs *la) {
+  la->wbf = mlp->wbf;
+  la->master = mlp->master;
+  la->norm = mlp->norm;
+}
+
 namespace {
 
 int mfail(prs_mlp *m, int code, const char *msg, hipError_t e = hipSuccess) {

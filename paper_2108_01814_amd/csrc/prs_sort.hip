@@ -190,8 +190,11 @@ hipError_t launch_gather_state(hipStream_t s, const Scratch &S, const Geom &G, c
   return hipGetLastError();
 }
 
+// Positions (and, when u and om are given, velocities) in sorted SoA order.
 __global__ void k_gather_pos(const int *__restrict__ perm, int n, Geom G,
-                             const double *__restrict__ x, double *xs, int *inv_perm) {
+                             const double *__restrict__ x, const double *__restrict__ u,
+                             const double *__restrict__ om, double *xs, double *us, double *ws,
+                             int *inv_perm, uint32_t *status) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int i = perm[j];
@@ -199,13 +202,21 @@ __global__ void k_gather_pos(const int *__restrict__ perm, int n, Geom G,
   uint32_t fl = 0;
   const double L[3] = {G.Lx, G.Ly, G.Lz};
   for (int a = 0; a < 3; ++a) xs[a * (size_t)n + j] = sane_coord(x[3 * i + a], L[a], a == 1, fl);
+  if (u)
+    for (int a = 0; a < 3; ++a) {
+      const double uv = u[3 * i + a], wv = om[3 * i + a];
+      if (!isfinite(uv) || !isfinite(wv)) fl |= kFlagNonFinite;
+      us[a * (size_t)n + j] = uv;
+      ws[a * (size_t)n + j] = wv;
+    }
+  if (fl && status) atomicOr(status, fl);
 }
 
 hipError_t launch_gather_pos(hipStream_t s, const Scratch &S, const Geom &G, const double *x,
-                             int n) {
+                             int n, const double *u, const double *om) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_pos, dim3((n + 255) / 256), dim3(256), 0, s, S.perm, n, G, x,
-                     S.xs[0], S.inv_perm);
+  hipLaunchKernelGGL(k_gather_pos, dim3((n + 255) / 256), dim3(256), 0, s, S.perm, n, G, x, u, om,
+                     S.xs[0], S.us[0], S.ws[0], S.inv_perm, S.status);
   return hipGetLastError();
 }
 
