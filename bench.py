@@ -113,6 +113,132 @@ def run_form(P, W, w, bed, precision, steps, warmup, torch, measure_touched=Fals
     return res
 
 
+def time_single_steps(P, ctx, uhat, bed, K, torch):
+    """K identical steps from the bed's initial state (the state is copied
+    before each step, outside the timed region); returns (ms per step,
+    stats of the last step, phase timing per step, F_h of the last step)."""
+    x0 = torch.as_tensor(bed.x, device="cuda")
+    u0 = torch.as_tensor(bed.u, device="cuda")
+    om0 = torch.as_tensor(bed.om, device="cuda")
+    n = x0.shape[0]
+    f = [torch.empty_like(a) for a in uhat]
+    Fh = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    Th = torch.empty_like(Fh)
+    total = 0.0
+    ctx.timing(True)
+    ctx.read_timing(reset=True)
+    for _ in range(K):
+        x, u, om = x0.clone(), u0.clone(), om0.clone()
+        H = P.History.zeros(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st = ctx.step(uhat, f, x, u, om, H, Fh, Th, zero_f=True)
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+    tm = ctx.read_timing(reset=True)
+    ctx.timing(False)
+    del f
+    phases = {k[3:]: v / K for k, v in tm.items() if k.startswith("ms_")}
+    return total / K * 1e3, st, phases, Fh
+
+
+def learned_comparison(P, W, w, bed, torch, n_snap, K, tol=1e-6, max_iter=10):
+    """FP32 + learned warm start against FP64 plain on the same bed and field,
+    both to the relative slip tolerance tol with at most max_iter iterations.
+
+    The network is trained first, on the GPU, on samples of the plain FP32
+    forcing (30 iterations) of the 22k-sphere workload: n_snap (bed, flow
+    time) snapshots, 2 % of the markers of each, Adam with batch 65,536 for
+    2,000 iterations."""
+    from paper_2108_01814_amd import learned as L
+
+    res = {"tol": tol, "max_iter": max_iter}
+    wt = W.WORKLOADS["c2-22k"]
+    t0 = time.time()
+    snaps = [(2000 + k // 10, k % 10) for k in range(n_snap)]
+    S = L.collect(wt, snaps, n_iter=30, keep=0.02, seed=0,
+                  progress=lambda k, st: (k + 1) % 25 == 0 and log(
+                      f"training samples: snapshot {k + 1}/{n_snap}"))
+    t_collect = time.time() - t0
+    t0 = time.time()
+    net, norm, losses = L.train(S, iters=2000, batch=65536, lr=1e-3, seed=0, log_every=500,
+                                progress=lambda it, l: log(f"training: iteration {it} loss {l:.4f}"))
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    held = L.collect(wt, [(9000, 0)], n_iter=30, keep=0.02, seed=1)
+    res["training"] = {"workload": wt.name, "snapshots": n_snap, "samples": int(S.X.shape[0]),
+                       "adam_iterations": 2000, "batch": 65536, "collect_s": t_collect,
+                       "train_s": t_train, "first_loss": losses[0][1], "final_loss": losses[-1][1],
+                       "held_out_loss": L.validation_loss(net, held, norm)}
+    del S, held
+    torch.cuda.empty_cache()
+    log(f"trained: {res['training']}")
+
+    modes = W.flow_modes(w, bed.bed_top)
+    fields = {P.F32: W.fluid_field(w, modes, device="cuda", dtype=torch.float32),
+              P.F64: W.fluid_field(w, modes, device="cuda", dtype=torch.float64)}
+    runs = {}
+
+    def form(name, precision, learned, tol_, max_iter_):
+        uhat = fields[precision]
+        with P.Context(params_for(P, W, w, precision, tol_mode=1, tol=tol_,
+                                  max_iter=max_iter_)) as ctx:
+            if learned:
+                ctx.set_learned(net)
+            time_single_steps(P, ctx, uhat, bed, 1, torch)     # warm-up
+            ms, st, ph, Fh = time_single_steps(P, ctx, uhat, bed, K, torch)
+        torch.cuda.empty_cache()
+        r = {"ms_per_step": ms, "iterations": st["iterations"], "rel_slip": st["rel_slip"],
+             "rejected_learned": st["rejected_learned"], "phases_ms_per_step": ph}
+        log(f"{name}: {ms:.1f} ms/step, {st['iterations']} iterations, "
+            f"final slip {st['rel_slip'][-1]:.4g}, rejected {st['rejected_learned']}")
+        runs[name] = r
+        return r, Fh
+
+    p64, Fh64 = form("fp64_plain", P.F64, False, tol, max_iter)
+    Fh64 = Fh64.cpu()
+    l32, Fh32 = form("fp32_learned", P.F32, True, tol, max_iter)
+    Fh32 = Fh32.cpu()
+    form("fp32_plain", P.F32, False, tol, max_iter)
+    res.update(runs)
+    res["speedup_at_tol"] = p64["ms_per_step"] / l32["ms_per_step"]
+    # equal accuracy: the slip FP64 plain ends at, reached by FP32 + learned
+    target = p64["rel_slip"][-1]
+    eq, Fh_eq = form("fp32_learned_equal_accuracy", P.F32, True, target * (1 + 1e-9), max_iter)
+    reached = eq["rel_slip"][-1] < target * (1 + 1e-9)
+    res["equal_accuracy"] = {
+        "target_slip": target, "reached": bool(reached),
+        "fp32_learned_iterations": eq["iterations"], "fp64_plain_iterations": p64["iterations"],
+        "fp32_learned_ms": eq["ms_per_step"], "fp64_plain_ms": p64["ms_per_step"],
+        "speedup": p64["ms_per_step"] / eq["ms_per_step"] if reached else None}
+    res.pop("fp32_learned_equal_accuracy", None)
+    # a looser tolerance, reached by both forms
+    a, _ = form("fp64_plain_1e-2", P.F64, False, 1e-2, max_iter)
+    b, _ = form("fp32_learned_1e-2", P.F32, True, 1e-2, max_iter)
+    res["to_1e-2"] = {"fp64_plain_ms": a["ms_per_step"], "fp64_plain_iterations": a["iterations"],
+                      "fp32_learned_ms": b["ms_per_step"],
+                      "fp32_learned_iterations": b["iterations"],
+                      "speedup": a["ms_per_step"] / b["ms_per_step"]}
+    for k in ("fp64_plain_1e-2", "fp32_learned_1e-2"):
+        res.pop(k, None)
+    # accuracy: F_h of each form against FP64 plain run to 60 iterations
+    ref, Fh_ref = form("fp64_plain_60", P.F64, False, 1e-12, 60)
+    Fh_ref = Fh_ref.cpu()
+    scale = float(Fh_ref.norm(dim=1).max())
+
+    def err(F):
+        return float((F - Fh_ref).norm(dim=1).max()) / scale
+
+    res["force_error_vs_fp64_60_iterations"] = {
+        "reference_final_slip": ref["rel_slip"][-1],
+        "fp64_plain": err(Fh64), "fp32_learned": err(Fh32),
+        "fp32_learned_equal_accuracy": err(Fh_eq.cpu())}
+    res.pop("fp64_plain_60", None)
+    del fields
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(W, w, bed, width=12.0):
     """The FP64 oracle, single-threaded, on a window of the same bed: the
     spheres with centres in a width x Ly x width column, the fluid field on
@@ -164,6 +290,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="c3-1m")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the FP32 + learned vs FP64 plain comparison")
+    ap.add_argument("--train-snapshots", type=int, default=200,
+                    help="training snapshots of the learned warm start")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -243,6 +373,9 @@ def main(argv=None):
             "phases_ms_per_step": {k[3:]: v / K64 for k, v in tm64.items() if k.startswith("ms_")},
             "fp32_speedup": t64 / t_step,
         }
+    if not args.no_learned:
+        out["learned_vs_fp64"] = learned_comparison(P, W, w, bed, torch, args.train_snapshots,
+                                                    max(1, min(K, 3)))
     if not args.no_cpu:
         cb = cpu_baseline(W, w, bed)
         cb.pop("rc", None)

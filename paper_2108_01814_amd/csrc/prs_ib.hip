@@ -257,28 +257,36 @@ __global__ __launch_bounds__(1024) void k_interp(
   }
   if constexpr (MODE == kInterpLearned) {
     // the network on the matrix cores: each wave evaluates its 64 markers as
-    // four 16-marker tiles; features and predictions pass through LDS
-    // the brick's LDS is reused: weights, then standardised inputs (BF16),
-    // then predictions (FP32)
+    // four 16-marker tiles.  The brick's LDS is reused for the weights, the
+    // standardised inputs (BF16) and the predictions (FP32).
     MlpLds &L = *reinterpret_cast<MlpLds *>(smem_raw);
-    unsigned short *fl = reinterpret_cast<unsigned short *>(smem_raw + kMlpLdsBytes);
-    float *yl = reinterpret_cast<float *>(fl + blockDim.x * kMlpIn);
+    // input fragments, tile-major: entry [tile][16 q + r] holds features
+    // 4q .. 4q+3 of marker r of the tile (tile = 16 consecutive lanes)
+    bf16x4 *fl = reinterpret_cast<bf16x4 *>(smem_raw + kMlpLdsBytes);
+    float *yl = reinterpret_cast<float *>(fl + blockDim.x * (kMlpIn / 4));
     __syncthreads();   // the brick is no longer read
     mlp_stage(L, la.wbf, la.master, false);
-    for (int k = 0; k < kMlpIn; ++k) {
-      float v = 0.f;
-      if (active && k < kMlpFeat)
-        v = (float)((featd[k] - (double)la.norm[k]) / (double)la.norm[kMlpIn + k]);
-      fl[threadIdx.x * kMlpIn + k] = to_bf16(v);
+    {
+      const int tile = threadIdx.x >> 4, r = threadIdx.x & 15;
+      for (int q = 0; q < kMlpIn / 4; ++q) {
+        float v[4];
+        for (int j = 0; j < 4; ++j) {
+          const int k = 4 * q + j;
+          v[j] = (active && k < kMlpFeat)
+                     ? (float)((featd[k] - (double)la.norm[k]) / (double)la.norm[kMlpIn + k])
+                     : 0.f;
+        }
+        fl[tile * 64 + 16 * q + r] = pack4(v[0], v[1], v[2], v[3]);
+      }
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, r = threadIdx.x & 15, q = (threadIdx.x >> 4) & 3;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     for (int t = 0; t < 4; ++t) {
-      const int slot = 64 * wave + 16 * t + r;
+      const int tile = 4 * wave + t;
       MlpFwd s;
-      mlp_forward_tile(L, lds4(&fl[slot * kMlpIn + 4 * q]), s);
+      mlp_forward_tile(L, fl[tile * 64 + lane], s);
       if (q == 0)
-        for (int i = 0; i < kMlpUsed; ++i) yl[slot * kMlpUsed + i] = s.y[i];
+        for (int i = 0; i < kMlpUsed; ++i) yl[(16 * tile + r) * kMlpUsed + i] = s.y[i];
     }
     __syncthreads();
     if (active) {

@@ -29,31 +29,79 @@ constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;
 constexpr int kMlpParams = kOffB3 + kMlpOut;   // 6288
 constexpr int kMlpNorm = 2 * kMlpIn + 2 * kMlpUsed;   // feature mean/std, target mean/std
 
-// FP32 -> BF16 bits, round to nearest even (NaN/inf passed through).
+// FP32 -> BF16 bits, round to nearest even (the gfx950 conversion
+// instruction).
 __device__ inline unsigned short to_bf16(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
 }
 
 __device__ inline float from_bf16(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Four FP32 values -> BF16 (round to nearest even), two per conversion.
 __device__ inline bf16x4 pack4(float a, float b, float c, float d) {
+  const bf16x2_t lo = __builtin_convertvector((f32x2){a, b}, bf16x2_t);
+  const bf16x2_t hi = __builtin_convertvector((f32x2){c, d}, bf16x2_t);
+  const unsigned ulo = __builtin_bit_cast(unsigned, lo), uhi = __builtin_bit_cast(unsigned, hi);
   bf16x4 v;
-  v.x = (short)to_bf16(a);
-  v.y = (short)to_bf16(b);
-  v.z = (short)to_bf16(c);
-  v.w = (short)to_bf16(d);
+  v.x = (short)(ulo & 0xffffu);
+  v.y = (short)(ulo >> 16);
+  v.z = (short)(uhi & 0xffffu);
+  v.w = (short)(uhi >> 16);
   return v;
 }
 
 __device__ inline bf16x4 pack4(const f32x4 &v) { return pack4(v.x, v.y, v.z, v.w); }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal distribution Phi(z) = erfc(-z / sqrt 2) / 2 and density
+// phi(z), branch-free.  erfc(x), x >= 0, is the Chebyshev fit of Press et
+// al., Numerical Recipes (2nd ed., sec. 6.2, "erfcc"), fractional error below
+// 1.2e-7 for every x: erfc(x) = t exp(-x^2 + P(t)), t = 1 / (1 + x / 2).
+__device__ inline void normal_cdf_pdf(float z, float &Phi, float &phi) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float ex2 = __builtin_amdgcn_exp2f(-x * x * 1.4426950408889634f);   // exp(-x^2)
+  const float half_erfc = 0.5f * t * ex2 * __builtin_amdgcn_exp2f(p * 1.4426950408889634f);
+  Phi = z >= 0.f ? 1.0f - half_erfc : half_erfc;
+  phi = ex2 * 0.39894228040143268f;   // exp(-z^2 / 2) / sqrt(2 pi)
+}
+
+// GELU(z) = z Phi(z), with the erfcc fit above evaluated in base 2 so that
+// one exponential serves: erfc(x) / 2 = t 2^(log2(e) (P(t) - x^2) - 1).
+__device__ inline float gelu(float z) {
+  constexpr float L2E = 1.4426950408889634f;
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  float p = 0.17087277f * L2E;
+  p = fmaf(p, t, -0.82215223f * L2E);
+  p = fmaf(p, t, 1.48851587f * L2E);
+  p = fmaf(p, t, -1.13520398f * L2E);
+  p = fmaf(p, t, 0.27886807f * L2E);
+  p = fmaf(p, t, -0.18628806f * L2E);
+  p = fmaf(p, t, 0.09678418f * L2E);
+  p = fmaf(p, t, 0.37409196f * L2E);
+  p = fmaf(p, t, 1.00002368f * L2E);
+  p = fmaf(p, t, -1.26551223f * L2E - 1.0f);
+  const float half_erfc = t * __builtin_amdgcn_exp2f(fmaf(z * (-0.5f * L2E), z, p));
+  return z * (z >= 0.f ? 1.0f - half_erfc : half_erfc);
+}
 
 __device__ inline float gelu_d(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  float Phi, phi;
+  normal_cdf_pdf(z, Phi, phi);
+  return Phi + z * phi;
 }
 
 __device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -65,30 +113,54 @@ __device__ inline bf16x4 lds4(const unsigned short *p) {
   return *reinterpret_cast<const bf16x4 *>(p);
 }
 
-// Weights staged in LDS as BF16: the parameter vector (W1, W2, W3 in their
-// row-major places; bias slots unused) plus transposed copies of W2 and W3
-// for the backward products, and the FP32 biases.
-struct MlpLds {
-  unsigned short w[kMlpParams];
-  unsigned short w2t[kMlpHid * kMlpHid];
-  unsigned short w3t[kMlpHid * kMlpOut];
+// Weights staged in LDS as BF16 MFMA operand fragments, fragment-major: entry
+// [..][lane] is the bf16x4 that lane (q = lane / 16, r = lane % 16) passes to
+// the product, so the 64 lanes of a wave read 512 consecutive bytes (no bank
+// conflicts, whatever the row length of the matrix):
+//   f1[t][lane]     = W1[16t + r][4q .. 4q+3]          (layer 1, output tile t)
+//   f2[t][kc][lane] = W2[16t + r][16kc + 4q .. +3]     (layer 2)
+//   f3[kc][lane]    = W3[r][16kc + 4q .. +3]           (layer 3)
+//   g2[t][kc][lane] = W2[16kc + 4q + j][16t + r], j = 0..3   (W2^T, backward)
+//   g3[t][lane]     = W3[4q + j][16t + r], j = 0..3          (W3^T, backward)
+// plus the FP32 biases.
+struct alignas(16) MlpLds {
+  bf16x4 f1[4][64];
+  bf16x4 f2[4][4][64];
+  bf16x4 f3[4][64];
+  bf16x4 g2[4][4][64];
+  bf16x4 g3[4][64];
   float b1[kMlpHid], b2[kMlpHid], b3[kMlpOut];
 };
 
 constexpr size_t kMlpLdsBytes = (sizeof(MlpLds) + 15) & ~(size_t)15;
 
-// Whole workgroup: copy the BF16 weights and FP32 biases into LDS.
+// Whole workgroup: stage the BF16 weights as fragments and the FP32 biases
+// (transposed: also the W2^T and W3^T fragments of the backward pass).
 __device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ wbf,
                                  const float *__restrict__ master, bool transposed) {
-  for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) L.w[i] = wbf[i];
+  auto frag = [&](int off) { return *reinterpret_cast<const bf16x4 *>(wbf + off); };
+  for (int e = threadIdx.x; e < 4 * 64; e += blockDim.x) {
+    const int t = e >> 6, lane = e & 63, r = lane & 15, q = lane >> 4;
+    L.f1[t][lane] = frag(kOffW1 + (16 * t + r) * kMlpIn + 4 * q);
+    L.f3[t][lane] = frag(kOffW3 + r * kMlpHid + 16 * t + 4 * q);
+  }
+  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+    const int t = e >> 8, kc = (e >> 6) & 3, lane = e & 63, r = lane & 15, q = lane >> 4;
+    L.f2[t][kc][lane] = frag(kOffW2 + (16 * t + r) * kMlpHid + 16 * kc + 4 * q);
+  }
   if (transposed) {
-    for (int i = threadIdx.x; i < kMlpHid * kMlpHid; i += blockDim.x) {
-      const int r = i / kMlpHid, c = i % kMlpHid;   // w2t[r][c] = W2[c][r]
-      L.w2t[i] = wbf[kOffW2 + c * kMlpHid + r];
+    for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+      const int t = e >> 8, kc = (e >> 6) & 3, lane = e & 63, r = lane & 15, q = lane >> 4;
+      bf16x4 v;
+      for (int j = 0; j < 4; ++j)
+        v[j] = (short)wbf[kOffW2 + (16 * kc + 4 * q + j) * kMlpHid + 16 * t + r];
+      L.g2[t][kc][lane] = v;
     }
-    for (int i = threadIdx.x; i < kMlpHid * kMlpOut; i += blockDim.x) {
-      const int r = i / kMlpOut, c = i % kMlpOut;   // w3t[r][c] = W3[c][r]
-      L.w3t[i] = wbf[kOffW3 + c * kMlpHid + r];
+    for (int e = threadIdx.x; e < 4 * 64; e += blockDim.x) {
+      const int t = e >> 6, lane = e & 63, r = lane & 15, q = lane >> 4;
+      bf16x4 v;
+      for (int j = 0; j < 4; ++j) v[j] = (short)wbf[kOffW3 + (4 * q + j) * kMlpHid + 16 * t + r];
+      L.g3[t][lane] = v;
     }
   }
   for (int i = threadIdx.x; i < kMlpHid; i += blockDim.x) {
@@ -108,31 +180,28 @@ struct MlpFwd {
 // Forward pass of one tile.  xb: B operand of the standardised input, lane
 // (q, r) holding features 4q..4q+3 of marker r.
 __device__ inline void mlp_forward_tile(const MlpLds &L, bf16x4 xb, MlpFwd &s) {
-  const int r = threadIdx.x & 15, q = (threadIdx.x >> 4) & 3;
+  const int lane = threadIdx.x & 63, q = lane >> 4;
   s.xb = xb;
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 z = mfma(lds4(&L.w[kOffW1 + (16 * t + r) * kMlpIn + 4 * q]), xb, zero);
-    for (int i = 0; i < 4; ++i) z[i] += L.b1[16 * t + 4 * q + i];
+    const f32x4 b = *reinterpret_cast<const f32x4 *>(&L.b1[16 * t + 4 * q]);
+    f32x4 z = mfma(L.f1[t][lane], xb, b);
     s.z1[t] = z;
     s.a1b[t] = pack4(gelu(z[0]), gelu(z[1]), gelu(z[2]), gelu(z[3]));
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 z = zero;
+    f32x4 z = *reinterpret_cast<const f32x4 *>(&L.b2[16 * t + 4 * q]);
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc)
-      z = mfma(lds4(&L.w[kOffW2 + (16 * t + r) * kMlpHid + 16 * kc + 4 * q]), s.a1b[kc], z);
-    for (int i = 0; i < 4; ++i) z[i] += L.b2[16 * t + 4 * q + i];
+      z = mfma(L.f2[t][kc][lane], s.a1b[kc], z);
     s.z2[t] = z;
     s.a2b[t] = pack4(gelu(z[0]), gelu(z[1]), gelu(z[2]), gelu(z[3]));
   }
-  f32x4 y = zero;
+  f32x4 y = *reinterpret_cast<const f32x4 *>(&L.b3[4 * q]);
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc)
-    y = mfma(lds4(&L.w[kOffW3 + r * kMlpHid + 16 * kc + 4 * q]), s.a2b[kc], y);
-  for (int i = 0; i < 4; ++i) y[i] += L.b3[4 * q + i];
+    y = mfma(L.f3[kc][lane], s.a2b[kc], y);
   s.y = y;
 }
 

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_train(
     bf16x4 dz2b[4], dz1b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const f32x4 da = mfma(lds4(&L.w3t[(16 * t + r) * kMlpOut + 4 * q]), dyb, zero);
+      const f32x4 da = mfma(L.g3[t][threadIdx.x & 63], dyb, zero);
       for (int i = 0; i < 4; ++i) dz2[t][i] = da[i] * gelu_d(s.z2[t][i]);
       dz2b[t] = pack4(dz2[t]);
     }
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_train(
       f32x4 da = zero;
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc)
-        da = mfma(lds4(&L.w2t[(16 * t + r) * kMlpHid + 16 * kc + 4 * q]), dz2b[kc], da);
+        da = mfma(L.g2[t][kc][threadIdx.x & 63], dz2b[kc], da);
       for (int i = 0; i < 4; ++i) dz1[t][i] = da[i] * gelu_d(s.z1[t][i]);
       dz1b[t] = pack4(dz1[t]);
     }
