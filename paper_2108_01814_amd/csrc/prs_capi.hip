@@ -342,7 +342,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   (void)hipGetDevice(&c->device);
   {
     hipDeviceProp_t prop;
-    const size_t need = (size_t)nb * nb * nb * (q.precision == PRS_F64 ? 8 : 4) + 4096;
+    const size_t need = brick_bytes(nb, q.precision == PRS_F64 ? 8 : 4) + 4096;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && need > prop.sharedMemPerBlock) {
       delete c;
       return PRS_EINVAL;
@@ -620,7 +620,7 @@ int prs_set_learned(prs_ctx *c, const prs_mlp *mlp) {
   if (!c) return PRS_EINVAL;
   if (mlp) {
     const int nb = brick_edge(c->p.radius, c->p.h);
-    const size_t brick = (size_t)nb * nb * nb * (c->p.precision == PRS_F64 ? 8 : 4);
+    const size_t brick = brick_bytes(nb, c->p.precision == PRS_F64 ? 8 : 4);
     const size_t need = std::max(brick, learned_lds_bytes(c->p.n_markers)) + 4096;
     hipDeviceProp_t prop;
     HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));

@@ -67,6 +67,11 @@ hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl) {
 
 int brick_edge(double R, double h) { return (int)std::ceil(2.0 * R / h) + 5; }
 
+size_t brick_bytes(int nb, int esz) {
+  const int vec = 16 / esz;
+  return (size_t)nb * nb * ((nb + vec - 1) / vec * vec) * esz;
+}
+
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
 size_t learned_lds_bytes(int nl) {
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
     double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *brick = reinterpret_cast<T *>(smem_raw);
   if (NB > 0) nb = NB;
   const int p = xcd_item(blockIdx.x, n);
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(1024) void k_interp(
                         up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
   const T tadt = (T)adt;
-  const int nb2 = nb * nb, nb3 = nb2 * nb;
+  const int nb2 = nb * nb;
   int lo[3][3];
   for (int c = 0; c < 3; ++c)
     for (int a = 0; a < 3; ++a) lo[c][a] = brick_lo(xp[a], G.R, G.inv_h, stagger(c, a)) - 1;
@@ -165,44 +170,61 @@ __global__ __launch_bounds__(1024) void k_interp(
   // one component at a time.
   for (int pass = 0; pass < (ALL3 ? 1 : 3); ++pass) {
     const int c0 = ALL3 ? 0 : pass, nc = ALL3 ? 3 : 1;
-    const int total = nc * nb3;
     __syncthreads();   // the previous pass's brick is no longer read
-    // x-rows of the brick: XL lanes per row (nb rounded up to a power of two),
-    // so the index arithmetic is done per row rather than per element
-    (void)total;
-    const int XL = nb <= 16 ? 16 : (nb <= 32 ? 32 : 64);
-    const int bx = threadIdx.x & (XL - 1);
-    const int rows_per = blockDim.x / XL;
-    const int nrows = nc * nb2;
+    // x-rows of the brick in chunks of VEC elements (16 bytes): one vector
+    // load per chunk, element-wise wrapped loads only for chunks that cross
+    // the periodic x boundary; rows padded to the pitch P in LDS
+    constexpr int VEC = 16 / sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    const int P = brick_pitch_c<T>(nb);
+    const int CPR = P / VEC;
+    const int nitems = nc * nb2 * CPR;
+    const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
     constexpr int kBrickUnroll = BrickUnroll<T>::value;
-    for (int row0 = threadIdx.x / XL; row0 < nrows; row0 += rows_per * kBrickUnroll) {
-      T v[kBrickUnroll];
+    for (int it0 = threadIdx.x; it0 < nitems; it0 += blockDim.x * kBrickUnroll) {
+      vec_t v[kBrickUnroll];
 #pragma unroll
       for (int u = 0; u < kBrickUnroll; ++u) {
-        const int row = row0 + u * rows_per;
-        v[u] = (T)0;
-        if (row < nrows && bx < nb) {
+        const int it = it0 + u * blockDim.x;
+        v[u] = (vec_t)(T)0;
+        if (it < nitems) {
+          const int row = it / CPR, ch = it - row * CPR;
           const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
           const int rr = row - cc * nb2;
           const int bz = rr / nb, by = rr - bz * nb;
           const int j = lo[c][1] + by;
           if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
-            const int i = wrap_once(lo[c][0] + bx, G.nx), k = wrap_once(lo[c][2] + bz, G.nz);
-            const int nyc = G.ny + (c == 1 ? 1 : 0);
-            const size_t g = ((size_t)k * nyc + j) * G.nx + i;
-            const T *Ap = c == 0 ? a0 : (c == 1 ? a1 : a2);
-            v[u] = Ap[g];
-            if (MODE == kInterpMDF) {
-              const T *Bp = c == 0 ? b0 : (c == 1 ? b1 : b2);
-              v[u] += tadt * Bp[g];
+            const int k = wrap_once(lo[c][2] + bz, G.nz);
+            const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
+            const int x0 = lo[c][0] + ch * VEC;
+            const T *Ap = (c == 0 ? a0 : (c == 1 ? a1 : a2)) + rowg;
+            const T *Bp = (c == 0 ? b0 : (c == 1 ? b1 : b2)) + rowg;
+            if (x0 >= 0 && x0 + VEC <= G.nx) {
+              __builtin_memcpy(&v[u], Ap + x0, sizeof(vec_t));
+              if (MODE == kInterpMDF) {
+                vec_t bv;
+                __builtin_memcpy(&bv, Bp + x0, sizeof(vec_t));
+                v[u] += tadt * bv;
+              }
+            } else {
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) {
+                const int i = wrap_once(x0 + e, G.nx);
+                T a = Ap[i];
+                if (MODE == kInterpMDF) a += tadt * Bp[i];
+                v[u][e] = a;
+              }
             }
           }
         }
       }
 #pragma unroll
       for (int u = 0; u < kBrickUnroll; ++u) {
-        const int row = row0 + u * rows_per;
-        if (row < nrows && bx < nb) brick[row * nb + bx] = v[u];
+        const int it = it0 + u * blockDim.x;
+        if (it < nitems) {
+          const int row = it / CPR, ch = it - row * CPR;
+          *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v[u];
+        }
       }
     }
     __syncthreads();
@@ -213,14 +235,14 @@ __global__ __launch_bounds__(1024) void k_interp(
         make_stencil<T>(G, c, X, S);
         int b[3];
         for (int a = 0; a < 3; ++a) b[a] = min(max(S.ic[a] - 1 - lo[c][a], 0), nb - 3);
-        const T *bk = brick + cc * nb3;
+        const T *bk = brick + cc * nb2 * P;
         T sum = 0;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj) {
             const T wzy = S.w[2][kk] * S.w[1][jj];
-            const T *row = bk + ((b[2] + kk) * nb + (b[1] + jj)) * nb + b[0];
+            const T *row = bk + ((b[2] + kk) * nb + (b[1] + jj)) * P + b[0];
 #pragma unroll
             for (int ii = 0; ii < 3; ++ii) sum += row[ii] * (wzy * S.w[0][ii]);
           }
@@ -362,7 +384,7 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
                              const int *order, const LearnArgs &la = LearnArgs{}) {
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
-  const size_t one = sizeof(T) * nb * nb * nb;
+  const size_t one = sizeof(T) * nb * nb * brick_pitch_c<T>(nb);
   const bool all3 = 3 * one <= PRS_BRICK_ALL3_MAX_BYTES;
   const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
   size_t lds = all3 ? 3 * one : one;
@@ -510,7 +532,77 @@ struct TileAcc<float> {
 
 constexpr int kTileCand = 256;     // spheres gathered by one tile
 constexpr int kTileThreads = PRS_TILE_THREADS;
+constexpr int kTileList = 2048;    // culled markers buffered before accumulation
 static_assert(kTileThreads >= kTileCand, "one scan lane per candidate");
+static_assert(kTileList >= 2 * kTileThreads, "a round must fit after a flush check");
+static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
+
+// One marker's contribution to a tile: weights of the three staggered
+// stencils, in-tile masks, and LDS atomic adds of value * weight * dV / h^3.
+template <typename T, int SRC, int TX, int TY, int TZ>
+__device__ inline void spread_marker(const Geom &G, const double X[3], const T *__restrict__ src,
+                                     const int *__restrict__ perm, int k, int l, size_t M,
+                                     T scale, int i0, int j0, int k0,
+                                     typename TileAcc<T>::type *acc) {
+  using A_t = typename TileAcc<T>::type;
+  constexpr int NODES = TX * TY * TZ;
+  T v[3];
+  if (SRC == 0) {
+    const size_t m = (size_t)k * G.nl + l;
+    for (int c = 0; c < 3; ++c) v[c] = src[c * M + m];
+  } else {
+    const size_t m = (size_t)perm[k] * G.nl + l;
+    for (int c = 0; c < 3; ++c) v[c] = src[3 * m + c];
+  }
+  // Per axis only two stencils exist: nodes on cell faces (stagger 0, the
+  // component along that axis) and at cell centres (stagger 1/2, the other
+  // two).  Evaluate each once, with its local tile indices and in-tile mask.
+  // (Adding zero-weight terms at clamped indices instead of masking measured
+  // slower: the accumulation is bound by LDS atomic throughput.)
+  T w[3][2][3];
+  int li[3][2][3];
+  unsigned msk[3][2];
+  const int tlen[3] = {TX, TY, TZ}, t0[3] = {i0, j0, k0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      int ic;
+      kernel3<T>(X[a] * G.inv_h - (o ? 0.5 : 0.0), ic, w[a][o]);
+      unsigned m = 0;
+      for (int t = 0; t < 3; ++t) {
+        int node = ic - 1 + t;
+        if (a == 0) node = wrap_once(node, G.nx);
+        if (a == 2) node = wrap_once(node, G.nz);
+        // y rows outside the fluid (and the wall faces of v) take no part
+        const bool row_ok = a != 1 || (node >= (o ? 0 : 1) && node <= G.ny - 1);
+        const int loc = node - t0[a];
+        li[a][o][t] = loc;
+        if (row_ok && loc >= 0 && loc < tlen[a]) m |= 1u << t;
+      }
+      msk[a][o] = m;
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
+    const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
+    if (!(mx && my && mz)) continue;
+    const A_t val = (A_t)(v[c] * scale);
+    A_t *A = acc + c * NODES;
+    for (int kk = 0; kk < 3; ++kk) {
+      if (!(mz >> kk & 1u)) continue;
+      for (int jj = 0; jj < 3; ++jj) {
+        if (!(my >> jj & 1u)) continue;
+        const T wzy = w[2][oz][kk] * w[1][oy][jj];
+        const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * TX;
+        for (int ii = 0; ii < 3; ++ii) {
+          if (!(mx >> ii & 1u)) continue;
+          atomicAdd(&A[base + li[0][ox][ii]], val * (A_t)(wzy * w[0][ox][ii]));
+        }
+      }
+    }
+  }
+}
 
 // SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
 //        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
@@ -529,6 +621,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   __shared__ int c_pref[kTileCand + 1];
   __shared__ double c_x[kTileCand][3];
   __shared__ int c_n;
+  __shared__ unsigned c_list[kTileList];   // culled (candidate << 10 | marker)
+  __shared__ int c_list_n;
 
   const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + 1 + TY - 1) / TY,
             ntz = (G.nz + TZ - 1) / TZ;
@@ -554,7 +648,10 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   const double mhw[3] = {(0.5 * TX + 1.25) * h + 1e-9 * h, (0.5 * TY + 1.25) * h + 1e-9 * h,
                          (0.5 * TZ + 1.25) * h + 1e-9 * h};
 
-  if (threadIdx.x == 0) c_n = 0;
+  if (threadIdx.x == 0) {
+    c_n = 0;
+    c_list_n = 0;
+  }
   __syncthreads();
   {
     const int cxl = (int)floor(lo[0] / C.csx), cxh = (int)floor(hi[0] / C.csx);
@@ -631,75 +728,52 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   const int total = c_pref[kTileCand];
   const T scale = (T)(G.dV * G.inv_h * G.inv_h * G.inv_h);
   const size_t M = N * nl;
-  for (int item = threadIdx.x; item < total; item += blockDim.x) {
-    int a = 0, b = kTileCand;   // largest s with c_pref[s] <= item
-    while (b - a > 1) {
-      const int mid = (a + b) >> 1;
-      if (c_pref[mid] <= item) a = mid; else b = mid;
-    }
-    const int s = a;
-    const int l = c_l0[s] + (item - c_pref[s]);
-    const int k = c_idx[s];
-    const double X[3] = {c_x[s][0] + R * templ[3 * l], c_x[s][1] + R * templ[3 * l + 1],
-                         c_x[s][2] + R * templ[3 * l + 2]};
-    // cheap rejection: a marker outside the tile's reach box touches none of
-    // its nodes (conservative; the exact test is the stencil below)
-    if (fabs(min_image(X[0] - mctr[0], G.Lx)) > mhw[0] || fabs(X[1] - mctr[1]) > mhw[1] ||
-        fabs(min_image(X[2] - mctr[2], G.Lz)) > mhw[2])
-      continue;
-    T v[3];
-    if (SRC == 0) {
-      const size_t m = (size_t)k * nl + l;
-      for (int c = 0; c < 3; ++c) v[c] = src[c * M + m];
-    } else {
-      const size_t m = (size_t)perm[k] * nl + l;
-      for (int c = 0; c < 3; ++c) v[c] = src[3 * m + c];
-    }
-    // Per axis only two stencils exist: nodes on cell faces (stagger 0, the
-    // component along that axis) and at cell centres (stagger 1/2, the other
-    // two).  Evaluate each once, with its local tile indices and in-tile mask.
-    T w[3][2][3];
-    int li[3][2][3];
-    unsigned msk[3][2];
-    const int tlen[3] = {TX, TY, TZ}, t0[3] = {i0, j0, k0};
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int o = 0; o < 2; ++o) {
-        int ic;
-        kernel3<T>(X[a] * G.inv_h - (o ? 0.5 : 0.0), ic, w[a][o]);
-        unsigned m = 0;
-        for (int t = 0; t < 3; ++t) {
-          int node = ic - 1 + t;
-          if (a == 0) node = wrap_once(node, G.nx);
-          if (a == 2) node = wrap_once(node, G.nz);
-          // y rows outside the fluid (and the wall faces of v) take no part
-          const bool row_ok = a != 1 || (node >= (o ? 0 : 1) && node <= G.ny - 1);
-          const int loc = node - t0[a];
-          li[a][o][t] = loc;
-          if (row_ok && loc >= 0 && loc < tlen[a]) m |= 1u << t;
-        }
-        msk[a][o] = m;
+  // Rounds of blockDim items (sphere, marker) of the y-bands: cull each item
+  // by the tile's reach box and append the survivors to an LDS list (wave
+  // ballot + one LDS atomic per wave); once the list could overflow, or at
+  // the end, every lane takes one listed marker for the stencil and the LDS
+  // atomics, so that work runs on full waves.
+  const int lane = threadIdx.x & 63;
+  for (int base0 = 0; base0 < total; base0 += blockDim.x) {
+    const int item = base0 + threadIdx.x;
+    bool pass = false;
+    unsigned code = 0;
+    if (item < total) {
+      int a = 0, b = kTileCand;   // largest s with c_pref[s] <= item
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (c_pref[mid] <= item) a = mid; else b = mid;
       }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
-      const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
-      if (!(mx && my && mz)) continue;
-      const A_t val = (A_t)(v[c] * scale);
-      A_t *A = acc + c * NODES;
-      for (int kk = 0; kk < 3; ++kk) {
-        if (!(mz >> kk & 1u)) continue;
-        for (int jj = 0; jj < 3; ++jj) {
-          if (!(my >> jj & 1u)) continue;
-          const T wzy = w[2][oz][kk] * w[1][oy][jj];
-          const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * TX;
-          for (int ii = 0; ii < 3; ++ii) {
-            if (!(mx >> ii & 1u)) continue;
-            atomicAdd(&A[base + li[0][ox][ii]], val * (A_t)(wzy * w[0][ox][ii]));
-          }
-        }
+      const int l = c_l0[a] + (item - c_pref[a]);
+      const double X0 = c_x[a][0] + R * templ[3 * l], X1 = c_x[a][1] + R * templ[3 * l + 1],
+                   X2 = c_x[a][2] + R * templ[3 * l + 2];
+      // a marker outside the tile's reach box touches none of its nodes
+      // (conservative; the exact test is the stencil mask)
+      pass = fabs(min_image(X0 - mctr[0], G.Lx)) <= mhw[0] && fabs(X1 - mctr[1]) <= mhw[1] &&
+             fabs(min_image(X2 - mctr[2], G.Lz)) <= mhw[2];
+      code = ((unsigned)a << 10) | (unsigned)l;
+    }
+    const unsigned long long ball = __ballot(pass);
+    int wbase = 0;
+    if (lane == 0 && ball) wbase = atomicAdd(&c_list_n, __popcll(ball));
+    wbase = __shfl(wbase, 0);
+    if (pass) c_list[wbase + __popcll(ball & ((1ull << lane) - 1ull))] = code;
+    __syncthreads();
+    const int listed = c_list_n;
+    const bool flush = listed > kTileList - (int)blockDim.x || base0 + (int)blockDim.x >= total;
+    __syncthreads();   // every lane has read the count before the next round appends
+    if (flush) {
+      for (int it = threadIdx.x; it < listed; it += blockDim.x) {
+        const unsigned cd = c_list[it];
+        const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
+        const int k = c_idx[sc];
+        const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
+                             c_x[sc][2] + R * templ[3 * l + 2]};
+        spread_marker<T, SRC, TX, TY, TZ>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
       }
+      __syncthreads();
+      if (threadIdx.x == 0) c_list_n = 0;
+      __syncthreads();
     }
   }
   __syncthreads();

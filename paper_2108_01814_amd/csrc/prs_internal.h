@@ -106,6 +106,12 @@ hipError_t launch_writeback(hipStream_t s, const Scratch &S, double *x, double *
 hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
 
 int brick_edge(double R, double h);
+// LDS bytes of one component's interpolation brick (x-rows padded to 16 bytes).
+size_t brick_bytes(int nb, int esz);
+template <typename T>
+__host__ __device__ constexpr int brick_pitch_c(int nb) {
+  return (nb + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T)) * (16 / (int)sizeof(T));
+}
 template <typename T>
 hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, const T *gu,
                                const T *gv, const T *gw, const double *x, const double *up,
