@@ -1,0 +1,91 @@
+"""Precision of the two forms against the FP64 oracle, per output, over a
+trajectory: the 512-sphere C1 bed stepped 20 times (3 forcing iterations and
+20 substeps per step, a new fluid field each step), both sides carrying their
+own state.  After the first step the bounds are the parity tolerances (FP64
+1e-11, FP32 1e-5); later steps are reported (differences grow through the
+contacts) and bounded loosely."""
+import numpy as np
+import pytest
+
+from helpers import fields_for, oracle_params, prs_params, rel_err
+from paper_2108_01814_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 20
+REPORT = (1, 5, 20)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    import paper_2108_01814_amd as P
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.lib()
+    return oracle
+
+
+def errors(gpu, ref):
+    return {
+        "F_h": rel_err(gpu["Fh"], ref["Fh"]), "T_h": rel_err(gpu["Th"], ref["Th"]),
+        "f": max(rel_err(gpu["f"][c], ref["f"][c]) for c in range(3)),
+        "x": float(np.abs(gpu["x"] - ref["x"]).max()), "u": rel_err(gpu["u"], ref["u"]),
+        "om": rel_err(gpu["om"], ref["om"]), "delta_t": rel_err(gpu["dt"], ref["dt"]),
+        "partners": int((gpu["partner"] != ref["partner"]).sum()),
+    }
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+def test_trajectory_errors_per_output(P, orc, precision):
+    import torch
+
+    w = W.C1
+    bed = W.make_bed(w)
+    modes = W.flow_modes(w, bed.bed_top)
+    dt = torch.float64 if precision == 1 else torch.float32
+    x, u, om = (torch.as_tensor(a).cuda() for a in (bed.x, bed.u, bed.om))
+    xo, uo, oo = bed.x.copy(), bed.u.copy(), bed.om.copy()
+    po = oracle_params(orc, w)
+    Ho = orc.History(w.n)
+    rows = {}
+    with P.Context(prs_params(P, w, precision)) as ctx:
+        H = P.History.zeros(w.n)
+        g = None
+        for step in range(1, STEPS + 1):
+            g = [a.to(dtype=dt) for a in W.fluid_field(w, modes, step=step, device="cuda",
+                                                           dtype=torch.float64)]
+            f = [torch.zeros_like(a) for a in g]
+            Fh, Th, st = ctx.step(g, f, x, u, om, H, zero_f=True)
+            uh = [np.ascontiguousarray(a.double().cpu().numpy()) for a in g]
+            fo = [np.zeros_like(a) for a in uh]
+            rc, out = orc.step(po, uh, fo, xo, uo, oo, Ho)
+            assert rc == 0
+            if step in REPORT:
+                gpu = dict(Fh=Fh.cpu().numpy(), Th=Th.cpu().numpy(), x=x.cpu().numpy(),
+                           u=u.cpu().numpy(), om=om.cpu().numpy(),
+                           f=[a.double().cpu().numpy() for a in f],
+                           dt=H.delta_t.cpu().numpy(), partner=H.partner.cpu().numpy())
+                ref = dict(Fh=out["Fh"], Th=out["Th"], x=xo, u=uo, om=oo, f=fo, dt=Ho.dt,
+                           partner=Ho.partner)
+                rows[step] = errors(gpu, ref)
+                print(f"{'FP64' if precision else 'FP32'} step {step}: " +
+                      ", ".join(f"{k} {v:.2e}" if isinstance(v, float) else f"{k} {v}"
+                                for k, v in rows[step].items()), flush=True)
+    tol = 1e-11 if precision == 1 else 1e-5
+    first = rows[1]
+    for k in ("F_h", "T_h", "f", "x", "u", "om"):
+        assert first[k] < tol, (k, first[k])
+    assert first["partners"] == 0
+    last = rows[STEPS]
+    for k in ("F_h", "T_h", "u", "om"):
+        assert last[k] < 1e3 * tol, (k, last[k])
