@@ -530,6 +530,13 @@ struct TileAcc<float> {
   using type = typename std::conditional<PRS_SPREAD_ACC_F64 != 0, double, float>::type;
 };
 
+// Row pitch of the LDS accumulators: TX + PRS_SPREAD_PAD entries (one pad
+// entry spreads the rows of a tile over the banks: -8 % spreading time at
+// D/h = 10 on MI355X; two measured no better than none).
+#ifndef PRS_SPREAD_PAD
+#define PRS_SPREAD_PAD 1
+#endif
+
 constexpr int kTileCand = 256;     // spheres gathered by one tile
 constexpr int kTileThreads = PRS_TILE_THREADS;
 constexpr int kTileList = 2048;    // culled markers buffered before accumulation
@@ -539,13 +546,14 @@ static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
 
 // One marker's contribution to a tile: weights of the three staggered
 // stencils, in-tile masks, and LDS atomic adds of value * weight * dV / h^3.
-template <typename T, int SRC, int TX, int TY, int TZ>
+template <typename T, int SRC, int TX, int TY, int TZ, int PX>
 __device__ inline void spread_marker(const Geom &G, const double X[3], const T *__restrict__ src,
                                      const int *__restrict__ perm, int k, int l, size_t M,
                                      T scale, int i0, int j0, int k0,
                                      typename TileAcc<T>::type *acc) {
   using A_t = typename TileAcc<T>::type;
-  constexpr int NODES = TX * TY * TZ;
+  constexpr int NODES = TX * TY * TZ, NODES_P = PX * TY * TZ;
+  (void)NODES;
   T v[3];
   if (SRC == 0) {
     const size_t m = (size_t)k * G.nl + l;
@@ -588,13 +596,13 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
     const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
     if (!(mx && my && mz)) continue;
     const A_t val = (A_t)(v[c] * scale);
-    A_t *A = acc + c * NODES;
+    A_t *A = acc + c * NODES_P;
     for (int kk = 0; kk < 3; ++kk) {
       if (!(mz >> kk & 1u)) continue;
       for (int jj = 0; jj < 3; ++jj) {
         if (!(my >> jj & 1u)) continue;
         const T wzy = w[2][oz][kk] * w[1][oy][jj];
-        const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * TX;
+        const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * PX;
         for (int ii = 0; ii < 3; ++ii) {
           if (!(mx >> ii & 1u)) continue;
           atomicAdd(&A[base + li[0][ox][ii]], val * (A_t)(wzy * w[0][ox][ii]));
@@ -613,9 +621,9 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
     T *f0, T *f1, T *f2, uint32_t *status) {
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
-  constexpr int NODES = TX * TY * TZ;
+  constexpr int PX = TX + PRS_SPREAD_PAD, NODES_P = PX * TY * TZ;
   using A_t = typename TileAcc<T>::type;
-  __shared__ A_t acc[3 * NODES];
+  __shared__ A_t acc[3 * NODES_P];
   __shared__ int c_idx[kTileCand];
   __shared__ int c_l0[kTileCand];
   __shared__ int c_pref[kTileCand + 1];
@@ -705,7 +713,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     c_l0[s] = l0;
     c_pref[s] = cnt;
   }
-  for (int q = threadIdx.x; q < 3 * NODES; q += blockDim.x) acc[q] = (A_t)0;
+  for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) acc[q] = (A_t)0;
   __syncthreads();
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads; every thread takes part in the barriers)
@@ -769,7 +777,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
         const int k = c_idx[sc];
         const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
                              c_x[sc][2] + R * templ[3 * l + 2]};
-        spread_marker<T, SRC, TX, TY, TZ>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
+        spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
       }
       __syncthreads();
       if (threadIdx.x == 0) c_list_n = 0;
@@ -777,11 +785,12 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 3 * NODES; q += blockDim.x) {
+  for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) {
     const T add = (T)acc[q];
     if (acc[q] == (A_t)0) continue;
-    const int c = q / NODES, r = q - c * NODES;
-    const int lz = r / (TX * TY), ly = (r / TX) % TY, lx = r % TX;
+    const int c = q / NODES_P, r = q - c * NODES_P;
+    const int lz = r / (PX * TY), ly = (r / PX) % TY, lx = r % PX;
+    if (lx >= TX) continue;
     const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
     const int nyc = G.ny + (c == 1 ? 1 : 0);
     if (i >= G.nx || j >= nyc || k >= G.nz) continue;
