@@ -540,7 +540,7 @@ struct TileAcc<float> {
 constexpr int kTileCand = 256;     // spheres gathered by one tile
 constexpr int kTileThreads = PRS_TILE_THREADS;
 constexpr int kTileList = 2048;    // culled markers buffered before accumulation
-static_assert(kTileThreads >= kTileCand, "one scan lane per candidate");
+static_assert(kTileThreads >= kTileCand && kTileCand % 64 == 0, "one scan lane per candidate");
 static_assert(kTileList >= 2 * kTileThreads, "a round must fit after a flush check");
 static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
 
@@ -716,21 +716,25 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) acc[q] = (A_t)0;
   __syncthreads();
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
-  // the first kTileCand threads; every thread takes part in the barriers)
+  // the first kTileCand threads): shuffles inside each wave, then the wave
+  // totals
   {
-    const int t = threadIdx.x;
-    const bool lane = t < kTileCand;
-    const int v = lane ? c_pref[t] : 0;
-    for (int off = 1; off < kTileCand; off <<= 1) {
-      const int add = (lane && t >= off) ? c_pref[t - off] : 0;
-      __syncthreads();
-      if (lane) c_pref[t] += add;
-      __syncthreads();
+    __shared__ int c_wsum[kTileCand / 64];
+    const int t = threadIdx.x, ln = t & 63;
+    const int v = t < kTileCand ? c_pref[t] : 0;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if (ln >= off) incl += y;
     }
-    const int incl = lane ? c_pref[t] : 0;
+    if (t < kTileCand && ln == 63) c_wsum[t >> 6] = incl;
     __syncthreads();
-    if (lane) c_pref[t] = incl - v;
-    if (t == kTileCand - 1) c_pref[kTileCand] = incl;
+    if (t < kTileCand) {
+      int base = 0;
+      for (int w = 0; w < (t >> 6); ++w) base += c_wsum[w];
+      c_pref[t] = base + incl - v;
+      if (t == kTileCand - 1) c_pref[kTileCand] = base + incl;
+    }
     __syncthreads();
   }
   const int total = c_pref[kTileCand];
