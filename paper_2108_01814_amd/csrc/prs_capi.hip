@@ -232,7 +232,10 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
   for (int it = 0;; ++it) {
     if (!tol_mode && it >= n_iter) break;
     HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, fc, n, adt, 0));
+    // the first pass after a cleared field with no initial force reads u-hat only
+    const T *fnone[3] = {nullptr, nullptr, nullptr};
+    HIP_TRY(c, launch_interp_mdf<T>(s, c->G, S, uh, it == 0 && !den_ready ? fnone : fc, n, adt,
+                                    0));
     HIP_TRY(c, phase_end(c, s, kInterp));
     HIP_TRY(c, launch_slip_reduce(s, S, n, it, 0));
     if (it == 0 && !den_ready) {

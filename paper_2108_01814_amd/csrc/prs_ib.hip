@@ -92,7 +92,8 @@ enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2, kInterpFeat = 3, kInter
 //                      force/torque sums.
 
 
-// MODE kInterpMDF  : sorted SoA state; u** = a + adt*b; writes dF [3][M],
+// MODE kInterpMDF  : sorted SoA state; u** = a + adt*b (b0 == NULL: a field
+//                    known to be zero, not read); writes dF [3][M],
 //                    the slip partial and the force/torque partials.
 // MODE kInterpDen  : sorted SoA state; a only; writes the zero-forcing slip
 //                    partial ||U_d - I[a]||^2.
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(1024) void k_interp(
             const T *Bp = (c == 0 ? b0 : (c == 1 ? b1 : b2)) + rowg;
             if (x0 >= 0 && x0 + VEC <= G.nx) {
               __builtin_memcpy(&v[u], Ap + x0, sizeof(vec_t));
-              if (MODE == kInterpMDF) {
+              if (MODE == kInterpMDF && b0) {
                 vec_t bv;
                 __builtin_memcpy(&bv, Bp + x0, sizeof(vec_t));
                 v[u] += tadt * bv;
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(1024) void k_interp(
               for (int e = 0; e < VEC; ++e) {
                 const int i = wrap_once(x0 + e, G.nx);
                 T a = Ap[i];
-                if (MODE == kInterpMDF) a += tadt * Bp[i];
+                if (MODE == kInterpMDF && b0) a += tadt * Bp[i];
                 v[u][e] = a;
               }
             }
