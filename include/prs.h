@@ -207,7 +207,7 @@ typedef struct prs_timing {
 /* ---- learned warm start ------------------------------------------------
  * Not part of the paper: a small network predicts each marker's initial
  * forcing, after which the unchanged multi-direct forcing runs, so the plain
- * method stays both the fallback and the judge.  Network: 16 inputs (12
+ * method stays both the fallback and the reference.  Network: 16 inputs (12
  * features zero-padded) -> 64 -> GELU -> 64 -> GELU -> 16 outputs (3 used),
  * exact-erf GELU, BF16 weights and activations on the matrix cores with FP32
  * accumulation, FP32 master weights trained by Adam (beta 0.9 / 0.999,

@@ -5,7 +5,7 @@
  * features, its loss gradient and the Adam update.  The learned warm start is
  * not part of the paper; its definition (sizes, BF16 weights with FP32
  * accumulation, exact-erf GELU, MSE on standardised targets, Adam) is the
- * build's own and is written out here as the reference.
+ * library's and is written out here as the reference.
  *
  * TEST INFRASTRUCTURE ONLY (see prs_oracle.c).
  *

@@ -1,8 +1,8 @@
 // Learned warm start: a 16 -> 64 -> GELU -> 64 -> GELU -> 16 perceptron on
 // gfx950 matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
-// accumulation).  The network is the build's own addition to the method
-// (the paper has no learned component); the plain multi-direct forcing runs
-// after it unchanged.
+// accumulation).  The network is an addition to the method (the paper has
+// no learned component); the plain multi-direct forcing runs after it
+// unchanged.
 //
 // Work layout: one wave evaluates 16 markers at a time with the markers as
 // the N dimension of every product, Z^T = W * X^T.  With the MFMA lane layout
