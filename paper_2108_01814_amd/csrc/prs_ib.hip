@@ -566,8 +566,9 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
   // Per axis only two stencils exist: nodes on cell faces (stagger 0, the
   // component along that axis) and at cell centres (stagger 1/2, the other
   // two).  Evaluate each once, with its local tile indices and in-tile mask.
-  // (Adding zero-weight terms at clamped indices instead of masking measured
-  // slower: the accumulation is bound by LDS atomic throughput.)
+  // (Adding zero-weight terms at clamped indices instead of masking, for all
+  // nodes or for the x-nodes of a row, measured slower: the extra LDS atomics
+  // cost more than the branches they save.)
   T w[3][2][3];
   int li[3][2][3];
   unsigned msk[3][2];
@@ -752,7 +753,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     bool pass = false;
     unsigned code = 0;
     if (item < total) {
-      int a = 0, b = kTileCand;   // largest s with c_pref[s] <= item
+      int a = 0, b = nc;   // largest s < nc with c_pref[s] <= item
       while (b - a > 1) {
         const int mid = (a + b) >> 1;
         if (c_pref[mid] <= item) a = mid; else b = mid;
@@ -790,18 +791,22 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) {
-    const T add = (T)acc[q];
-    if (acc[q] == (A_t)0) continue;
-    const int c = q / NODES_P, r = q - c * NODES_P;
-    const int lz = r / (PX * TY), ly = (r / PX) % TY, lx = r % PX;
-    if (lx >= TX) continue;
-    const int i = i0 + lx, j = j0 + ly, k = k0 + lz;
-    const int nyc = G.ny + (c == 1 ? 1 : 0);
-    if (i >= G.nx || j >= nyc || k >= G.nz) continue;
-    const size_t g = ((size_t)k * nyc + j) * G.nx + i;
-    T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
-    Fp[g] += add;
+  // write-back by x-rows: TX lanes per row, rows (component, z, y)
+  static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
+  {
+    const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
+    for (int row = threadIdx.x / TX; row < 3 * TZ * TY; row += kTileThreads / TX) {
+      const A_t a = acc[row * PX + lx];
+      if (a == (A_t)0 || i >= G.nx) continue;
+      const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
+      const int lz = rz / TY, ly = rz - lz * TY;
+      const int j = j0 + ly, k = k0 + lz;
+      const int nyc = G.ny + (c == 1 ? 1 : 0);
+      if (j >= nyc || k >= G.nz) continue;
+      const size_t g = ((size_t)k * nyc + j) * G.nx + i;
+      T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
+      Fp[g] += (T)a;
+    }
   }
 }
 
