@@ -597,17 +597,21 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
     const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
     const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
     if (!(mx && my && mz)) continue;
+    // weights in the accumulator precision: per node one multiply by the
+    // row's value val * wz * wy
     const A_t val = (A_t)(v[c] * scale);
+    const A_t wx[3] = {(A_t)w[0][ox][0], (A_t)w[0][ox][1], (A_t)w[0][ox][2]};
     A_t *A = acc + c * NODES_P;
     for (int kk = 0; kk < 3; ++kk) {
       if (!(mz >> kk & 1u)) continue;
+      const A_t vz = val * (A_t)w[2][oz][kk];
       for (int jj = 0; jj < 3; ++jj) {
         if (!(my >> jj & 1u)) continue;
-        const T wzy = w[2][oz][kk] * w[1][oy][jj];
-        const int base = (li[2][oz][kk] * TY + li[1][oy][jj]) * PX;
+        const A_t vzy = vz * (A_t)w[1][oy][jj];
+        A_t *rowp = A + (li[2][oz][kk] * TY + li[1][oy][jj]) * PX;
         for (int ii = 0; ii < 3; ++ii) {
           if (!(mx >> ii & 1u)) continue;
-          atomicAdd(&A[base + li[0][ox][ii]], val * (A_t)(wzy * w[0][ox][ii]));
+          atomicAdd(rowp + li[0][ox][ii], vzy * wx[ii]);
         }
       }
     }
