@@ -142,8 +142,12 @@ int prs_interpolate(prs_ctx *ctx, void *stream, const void *gu, const void *gv, 
 /* Diffusion / spreading (sec. 3.3), the adjoint of prs_interpolate:
  * f_c[node] += F_c * weight * dV / h^3 for every marker.  F: [n][n_markers][3];
  * fu, fv, fw: grid fields, accumulated into (accumulate != 0) or cleared
- * first (accumulate == 0).  Accumulation uses atomic adds, so the summation
- * order (and the last bits) may differ between runs.  Asynchronous. */
+ * first (accumulate == 0).  FP64 fields accumulate with floating-point atomic
+ * adds, so the summation order (and the last bits) may differ between runs;
+ * FP32 fields accumulate in 32-bit fixed point per tile of the grid (each
+ * addend rounded to 2^-30 of a bound on the tile's node sums), which is
+ * deterministic.  Non-finite marker values make the reached nodes NaN.
+ * Asynchronous. */
 int prs_spread(prs_ctx *ctx, void *stream, const double *x, int32_t n, const void *F, void *fu,
                void *fv, void *fw, int accumulate);
 

@@ -324,6 +324,22 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   G.R = q.radius;
   G.nl = q.n_markers;
   G.dV = M_PI * q.h * (12.0 * q.radius * q.radius + q.h * q.h) / (3.0 * q.n_markers);
+  {
+    // A node's stencil weights are products of three one-dimensional
+    // kernel values (each <= 2/3) and it is reached by markers within
+    // rho = 1.5 sqrt(3) h.  Those markers of one sphere lie on the part of
+    // the sphere inside a ball of radius rho, a cap of area at most
+    // 2 pi R (R - sqrt(R^2 - rho^2)) (the whole sphere when rho >= R), against
+    // 4 pi R^2 / n_markers per marker; the Fibonacci points are within a
+    // factor 1.5 of uniform, and four extra markers cover the cap's rim.
+    const double R = q.radius;
+    const double rho = 1.5 * std::sqrt(3.0) * q.h + 1e-9 * q.h;
+    const double area =
+        rho < R ? 2.0 * M_PI * R * (R - std::sqrt(R * R - rho * rho)) : 4.0 * M_PI * R * R;
+    const double per_marker = 4.0 * M_PI * R * R / q.n_markers;
+    const double markers = std::min((double)q.n_markers, std::ceil(1.5 * area / per_marker) + 4.0);
+    G.wsum_bound = markers * (8.0 / 27.0);
+  }
   // the stencil of a marker must not wrap twice around the periodic box
   if (!(G.Lx > q.radius + 3 * q.h) || !(G.Lz > q.radius + 3 * q.h)) {
     delete c;
@@ -396,6 +412,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.ft_acc, 12 * n);
   rc |= alloc(c, &S.ft_part, 12 * n);
   rc |= alloc(c, &S.slip_part, 2 * n);
+  rc |= alloc(c, &S.vmax, n);
   rc |= alloc(c, &S.slip_hist, PRS_MAX_SLIP + 1 + 256);
   rc |= alloc(c, &S.ncand, n);
   rc |= alloc(c, &S.cand, (size_t)kCandCap * n);

@@ -31,6 +31,9 @@ __device__ inline void comp_add(double &s, double &c, double s2, double c2) {
   c = c + c2 + e;
 }
 
+// max(a, b) that keeps a NaN of either argument.
+__device__ inline float nan_max(float a, float b) { return (b > a || b != b) ? b : a; }
+
 __device__ inline int wrap_once(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }

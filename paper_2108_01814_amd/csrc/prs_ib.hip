@@ -124,7 +124,8 @@ __global__ __launch_bounds__(1024) void k_interp(
     const T *__restrict__ b2, double adt, const double *__restrict__ xs,
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
-    double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la) {
+    double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la,
+    float *__restrict__ vmax_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *brick = reinterpret_cast<T *>(smem_raw);
   if (NB > 0) nb = NB;
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(1024) void k_interp(
   }
   Red red;
   red_zero(red);
+  float vm = 0.f;   // largest |value| this lane writes to out (MDF, learned)
   // features of the learned warm start: slip, normal, u_p, R omega_p
   double featd[kMlpFeat];
   if (MODE == kInterpFeat || MODE == kInterpLearned) {
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(1024) void k_interp(
         const T f0 = (T)((y * (double)la.norm[2 * kMlpIn + kMlpUsed + c] +
                           (double)la.norm[2 * kMlpIn + c]) / adt);
         out[c * M + m] = f0;
+        vm = nan_max(vm, fabsf((float)f0));
         d[c] = (double)f0;
       }
       red_set_ft(red, rl, d);
@@ -334,6 +337,7 @@ __global__ __launch_bounds__(1024) void k_interp(
         const T res = (T)Ud[c] - U[c];
         const T corr = res / tadt;
         out[c * M + m] = corr;
+        vm = nan_max(vm, fabsf((float)corr));
         d[c] = (double)corr;
         red.q[0] += (double)res * (double)res;
       }
@@ -345,8 +349,18 @@ __global__ __launch_bounds__(1024) void k_interp(
       }
     }
   }
-  block_reduce(red);
+  __shared__ float s_vmax[16];
+  if (MODE == kInterpMDF || MODE == kInterpLearned) {
+    for (int off = 32; off > 0; off >>= 1) vm = nan_max(vm, __shfl_xor(vm, off));
+    if ((threadIdx.x & 63) == 0) s_vmax[threadIdx.x >> 6] = vm;
+  }
+  block_reduce(red);   // (its barrier also publishes s_vmax)
   if (threadIdx.x == 0) {
+    if ((MODE == kInterpMDF || MODE == kInterpLearned) && vmax_out) {
+      float m = 0.f;
+      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) m = nan_max(m, s_vmax[wv]);
+      vmax_out[p] = m;
+    }
     if (MODE == kInterpMDF || MODE == kInterpLearned) {
       if (MODE == kInterpMDF) slip_part[p] = red.q[0];
       for (int k = 0; k < 6; ++k) {
@@ -365,16 +379,20 @@ void launch_interp_nb(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Ge
                       const double *templ, const T *a0, const T *a1, const T *a2, const T *b0,
                       const T *b1, const T *b2, double adt, const double *xs, const double *us,
                       const double *ws, int n, int nb, T *out, T *out2, double *slip_part,
-                      double *ft_part, const int *order, const LearnArgs &la) {
+                      double *ft_part, const int *order, const LearnArgs &la,
+                      float *vmax_out) {
   if (nb == 15)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 15>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
+                       vmax_out);
   else if (nb == 21)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 21>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
+                       vmax_out);
   else
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 0>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
+                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
+                       vmax_out);
 }
 
 template <typename T, int MODE>
@@ -382,7 +400,8 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
                              const T *a1, const T *a2, const T *b0, const T *b1, const T *b2,
                              double adt, const double *xs, const double *us, const double *ws,
                              int n, T *out, T *out2, double *slip_part, double *ft_part,
-                             const int *order, const LearnArgs &la = LearnArgs{}) {
+                             const int *order, const LearnArgs &la = LearnArgs{},
+                             float *vmax_out = nullptr) {
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
   const size_t one = sizeof(T) * nb * nb * brick_pitch_c<T>(nb);
@@ -392,10 +411,10 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
   if (MODE == kInterpLearned) lds = std::max(lds, learned_lds_bytes(G.nl));
   if (all3)
     launch_interp_nb<T, MODE, true>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
+                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out);
   else
     launch_interp_nb<T, MODE, false>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la);
+                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out);
   return hipGetLastError();
 }
 
@@ -417,7 +436,8 @@ hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, con
                                             nullptr, S.slip_part, nullptr, S.lane_order);
   return launch_interp_any<T, kInterpMDF>(s, G, S.templ, uh[0], uh[1], uh[2], f[0], f[1], f[2],
                                           adt, S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
-                                          S.slip_part, S.ft_part, S.lane_order);
+                                          S.slip_part, S.ft_part, S.lane_order, LearnArgs{},
+                                          S.vmax);
 }
 
 template <typename T>
@@ -437,7 +457,7 @@ hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S,
   return launch_interp_any<T, kInterpLearned>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
                                               nullptr, adt, S.xs[0], S.us[0], S.ws[0], n,
                                               (T *)S.dF, nullptr, S.slip_part, S.ft_part,
-                                              S.lane_order, la);
+                                              S.lane_order, la, S.vmax);
 }
 
 // target[caller marker][c] += adt * dF[c][sorted marker]
@@ -515,20 +535,23 @@ struct TileShape<float> : Shape3<PRS_TILE_F32> {};
 template <>
 struct TileShape<double> : Shape3<PRS_TILE_F64> {};
 
-// Accumulate the tiles of single-precision fields in double-precision LDS:
-// on gfx950 the LDS double-precision atomic add sustains about three times
-// the rate of the single-precision one in this access pattern (and the sums
-// are more accurate).
-#ifndef PRS_SPREAD_ACC_F64
-#define PRS_SPREAD_ACC_F64 1
-#endif
+// Tile accumulators in LDS.  Double-precision fields: double, with the LDS
+// double-precision atomic add.  Single-precision fields: 32-bit fixed point
+// with a per-tile unit (block floating point), added with the LDS integer
+// atomic -- on gfx950 it sustains about 1.5x the double-precision and 5x
+// the single-precision floating-point atomic add in this access pattern.
+// The unit is B / 2^30 with B a bound on any node's sum: wsum_bound (the
+// largest weight sum one sphere's markers can give a node) times
+// dV / h^3 times the sum over the tile's candidate spheres of their largest
+// |marker value|, so no sum can overflow; each addend is rounded to the unit
+// (about 22 bits relative to the tile's largest possible value, like FP32).
 template <typename T>
 struct TileAcc {
   using type = T;
 };
 template <>
 struct TileAcc<float> {
-  using type = typename std::conditional<PRS_SPREAD_ACC_F64 != 0, double, float>::type;
+  using type = int;
 };
 
 // Row pitch of the LDS accumulators: TX + PRS_SPREAD_PAD entries (one pad
@@ -547,6 +570,7 @@ static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
 
 // One marker's contribution to a tile: weights of the three staggered
 // stencils, in-tile masks, and LDS atomic adds of value * weight * dV / h^3.
+// scale: dV / h^3 (floating-point accumulators) or dV / h^3 / unit (fixed point).
 template <typename T, int SRC, int TX, int TY, int TZ, int PX>
 __device__ inline void spread_marker(const Geom &G, const double X[3], const T *__restrict__ src,
                                      const int *__restrict__ perm, int k, int l, size_t M,
@@ -597,21 +621,25 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
     const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
     const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
     if (!(mx && my && mz)) continue;
-    // weights in the accumulator precision: per node one multiply by the
-    // row's value val * wz * wy
-    const A_t val = (A_t)(v[c] * scale);
-    const A_t wx[3] = {(A_t)w[0][ox][0], (A_t)w[0][ox][1], (A_t)w[0][ox][2]};
+    // per node one multiply by the row's value val * wz * wy (in the field
+    // precision, or double for double accumulators)
+    using W_t = typename std::conditional<std::is_integral<A_t>::value, T, A_t>::type;
+    const W_t val = (W_t)(v[c] * scale);
+    const W_t wx[3] = {(W_t)w[0][ox][0], (W_t)w[0][ox][1], (W_t)w[0][ox][2]};
     A_t *A = acc + c * NODES_P;
     for (int kk = 0; kk < 3; ++kk) {
       if (!(mz >> kk & 1u)) continue;
-      const A_t vz = val * (A_t)w[2][oz][kk];
+      const W_t vz = val * (W_t)w[2][oz][kk];
       for (int jj = 0; jj < 3; ++jj) {
         if (!(my >> jj & 1u)) continue;
-        const A_t vzy = vz * (A_t)w[1][oy][jj];
+        const W_t vzy = vz * (W_t)w[1][oy][jj];
         A_t *rowp = A + (li[2][oz][kk] * TY + li[1][oy][jj]) * PX;
         for (int ii = 0; ii < 3; ++ii) {
           if (!(mx >> ii & 1u)) continue;
-          atomicAdd(rowp + li[0][ox][ii], vzy * wx[ii]);
+          if constexpr (std::is_integral<A_t>::value)
+            atomicAdd(rowp + li[0][ox][ii], (A_t)__float2int_rn(vzy * wx[ii]));
+          else
+            atomicAdd(rowp + li[0][ox][ii], vzy * wx[ii]);
         }
       }
     }
@@ -625,7 +653,7 @@ template <typename T, int SRC>
 __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
     const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
-    T *f0, T *f1, T *f2, uint32_t *status) {
+    const float *__restrict__ vmax, T *f0, T *f1, T *f2, uint32_t *status) {
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
   constexpr int PX = TX + PRS_SPREAD_PAD, NODES_P = PX * TY * TZ;
   using A_t = typename TileAcc<T>::type;
@@ -724,8 +752,11 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads): shuffles inside each wave, then the wave
   // totals
+  constexpr bool kFixed = std::is_integral<A_t>::value;
+  double vsum = 0.0;   // sum of the candidates' largest |marker value| (fixed point)
   {
     __shared__ int c_wsum[kTileCand / 64];
+    __shared__ double c_wvsum[kTileCand / 64];
     const int t = threadIdx.x, ln = t & 63;
     const int v = t < kTileCand ? c_pref[t] : 0;
     int incl = v;
@@ -734,7 +765,14 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
       if (ln >= off) incl += y;
     }
     if (t < kTileCand && ln == 63) c_wsum[t >> 6] = incl;
+    if (kFixed) {
+      double vs = t < nc ? (double)vmax[c_idx[t]] : 0.0;
+      for (int off = 32; off > 0; off >>= 1) vs += __shfl_xor(vs, off);
+      if (t < kTileCand && ln == 0) c_wvsum[t >> 6] = vs;
+    }
     __syncthreads();
+    if (kFixed)
+      for (int w = 0; w < kTileCand / 64; ++w) vsum += c_wvsum[w];
     if (t < kTileCand) {
       int base = 0;
       for (int w = 0; w < (t >> 6); ++w) base += c_wsum[w];
@@ -744,7 +782,13 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     __syncthreads();
   }
   const int total = c_pref[kTileCand];
-  const T scale = (T)(G.dV * G.inv_h * G.inv_h * G.inv_h);
+  const double dvh = G.dV * G.inv_h * G.inv_h * G.inv_h;
+  // fixed point: unit = B / 2^30; a non-finite bound (non-finite marker
+  // values) poisons the tile's nodes instead
+  const double bound = G.wsum_bound * dvh * vsum;
+  const bool poison = kFixed && !(bound < INFINITY);
+  const double unit = kFixed ? bound * (1.0 / 1073741824.0) : 1.0;
+  const T scale = (T)(kFixed ? (unit > 0.0 && !poison ? dvh / unit : 0.0) : dvh);
   const size_t M = N * nl;
   // Rounds of blockDim items (sphere, marker) of the y-bands: cull each item
   // by the tile's reach box and append the survivors to an LDS list (wave
@@ -801,7 +845,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
     for (int row = threadIdx.x / TX; row < 3 * TZ * TY; row += kTileThreads / TX) {
       const A_t a = acc[row * PX + lx];
-      if (a == (A_t)0 || i >= G.nx) continue;
+      if ((a == (A_t)0 && !poison) || i >= G.nx) continue;
       const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
       const int lz = rz / TY, ly = rz - lz * TY;
       const int j = j0 + ly, k = k0 + lz;
@@ -809,10 +853,46 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
       if (j >= nyc || k >= G.nz) continue;
       const size_t g = ((size_t)k * nyc + j) * G.nx + i;
       T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
-      Fp[g] += (T)a;
+      Fp[g] += poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
     }
   }
+  if (poison && threadIdx.x == 0) atomicOr(status, kFlagNonFinite);
 }
+
+// vmax[p] = largest |component| of the caller-ordered marker values of
+// sorted sphere p (NaN if any is NaN).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sphere_vmax(Geom G, const T *__restrict__ F,
+                                                      const int *__restrict__ perm, int n,
+                                                      float *vmax) {
+  __shared__ float wm[16];
+  const int p = xcd_item(blockIdx.x, n);
+  if (p < 0) return;
+  float m = 0.f;
+  if ((int)threadIdx.x < G.nl) {
+    const size_t q = ((size_t)perm[p] * G.nl + threadIdx.x) * 3;
+    for (int c = 0; c < 3; ++c) m = nan_max(m, fabsf((float)F[q + c]));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = nan_max(m, wm[w]);
+    vmax[p] = m;
+  }
+}
+
+template <typename T>
+hipError_t launch_sphere_vmax(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sphere_vmax<T>, dim3(xcd_grid(n)), dim3(block_for(G.nl)), 0, s, G, F,
+                     S.perm, n, S.vmax);
+  return hipGetLastError();
+}
+template hipError_t launch_sphere_vmax<float>(hipStream_t, const Geom &, const Scratch &, int,
+                                              const float *);
+template hipError_t launch_sphere_vmax<double>(hipStream_t, const Geom &, const Scratch &, int,
+                                               const double *);
 
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
@@ -821,14 +901,19 @@ hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, con
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
   const int ntiles =
       ((G.nx + TX - 1) / TX) * ((G.ny + 1 + TY - 1) / TY) * ((G.nz + TZ - 1) / TZ);
-  if (src_caller)
+  // caller values: their per-sphere maxima first (the correction buffer's are
+  // written by the interpolation pass that fills it)
+  if (src_caller) {
+    hipError_t e = launch_sphere_vmax<T>(s, G, S, n, src_caller);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_spread_tiles<T, 1>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
-                       G, C, S.start, S.xs[0], n, S.templ, src_caller, S.perm, f[0], f[1], f[2],
-                       S.status);
-  else
+                       G, C, S.start, S.xs[0], n, S.templ, src_caller, S.perm, S.vmax, f[0],
+                       f[1], f[2], S.status);
+  } else {
     hipLaunchKernelGGL((k_spread_tiles<T, 0>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
-                       G, C, S.start, S.xs[0], n, S.templ, (const T *)S.dF, S.perm, f[0], f[1],
-                       f[2], S.status);
+                       G, C, S.start, S.xs[0], n, S.templ, (const T *)S.dF, S.perm, S.vmax, f[0],
+                       f[1], f[2], S.status);
+  }
   return hipGetLastError();
 }
 
@@ -871,6 +956,7 @@ __global__ __launch_bounds__(1024) void k_marker_sums(Geom G, const double *__re
   const int l = threadIdx.x;
   Red red;
   red_zero(red);
+  float vm = 0.f;   // largest |value| this lane writes to out (MDF, learned)
   if (l < G.nl) {
     const double rl[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
     const size_t m = (size_t)perm[p] * G.nl + l;

@@ -32,6 +32,9 @@ struct Geom {
   double R;
   int nl;
   double dV;
+  // bound on the sum of one sphere's stencil weights at any node, in units
+  // of the sphere's largest marker value (fixed-point spreading)
+  double wsum_bound;
 };
 
 // Collision cells: an ncx*ncy*ncz partition of the box, cell edges >= the
@@ -66,6 +69,7 @@ struct Scratch {
   double *ft_acc;             // [12][n]: (sum, compensation) x (Fx Fy Fz Tx Ty Tz)
   double *ft_part;            // [12][n]: the same for the latest interpolation pass
   double *slip_part;          // [2][n]: slip^2 and zero-forcing slip^2 per sphere
+  float *vmax;                // [n]: largest |marker value| per sphere (latest spread source)
   double *slip_hist;          // [kMaxSlip + 1 + 256]: per pass, zero-forcing, block partials
   int *ncand, *cand;          // [n], [kCandCap][n]
   // contact history, internal SoA layout [slot][n], double-buffered
@@ -137,6 +141,8 @@ template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
                                T *f[3], int n, const T *src_caller);
 hipError_t launch_ft_commit(hipStream_t s, const Scratch &S, int n);
+template <typename T>
+hipError_t launch_sphere_vmax(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F);
 template <typename T>
 hipError_t launch_marker_sums(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F0);
 hipError_t launch_copy_scalar(hipStream_t s, const double *src, double *dst);

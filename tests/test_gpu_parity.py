@@ -94,9 +94,14 @@ def test_spread_parity(P, orc, precision):
         got0 = host64(fields)
     ref = [np.zeros(s) for s in orc.grid_shapes(oracle_params(orc, w))]
     orc.spread(oracle_params(orc, w), bed.x, Fd.cpu().double().numpy(), ref)
+    # FP64: a tenth of the path's bound.  FP32: the path's bound itself -- its
+    # tiles accumulate in 32-bit fixed point, each addend rounded to 2^-30 of
+    # a bound on the tile's node sums (about 2e-6 of the largest node value
+    # for these random, cancelling marker values)
+    tol = TOL[precision] / 10 if precision == 1 else TOL[precision]
     for c in range(3):
-        assert rel_err(got[c] - 0.25, ref[c]) < TOL[precision] / 10
-        assert rel_err(got0[c], ref[c]) < TOL[precision] / 10
+        assert rel_err(got[c] - 0.25, ref[c]) < tol
+        assert rel_err(got0[c], ref[c]) < tol
 
 
 def test_spread_is_adjoint_on_gpu(P):
