@@ -732,14 +732,23 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     if (threadIdx.x == 0) atomicOr(status, kFlagCand);
     nc = kTileCand;
   }
-  // markers of each sphere that can reach the tile in y: the template's
-  // y-component 1 - (2l+1)/N_L is monotone in l, so they form one index range
+  // markers of each sphere that can reach the tile: the template's
+  // y-component 1 - (2l+1)/N_L is monotone in l, so the markers within the
+  // tile's reach in y form one index range.  A centre a distance dx (dz)
+  // outside the markers' reach box in x (z) needs |t_x| >= dx/R and |t_z| >=
+  // dz/R, so t_x^2 + t_z^2 = 1 - t_y^2 >= (dx^2 + dz^2) / R^2: a band around
+  // the equator, which narrows the range further.
   const int nl = G.nl;
   const double ylo = (j0 - 1.5) * h, yhi = (j0 + TY + 1.0) * h;
   for (int s = threadIdx.x; s < kTileCand; s += blockDim.x) {
     int cnt = 0, l0 = 0;
     if (s < nc) {
-      const double thi = (yhi - c_x[s][1]) / R, tlo = (ylo - c_x[s][1]) / R;
+      double thi = (yhi - c_x[s][1]) / R, tlo = (ylo - c_x[s][1]) / R;
+      const double dx = fmax(fabs(min_image(c_x[s][0] - mctr[0], G.Lx)) - mhw[0], 0.0);
+      const double dz = fmax(fabs(min_image(c_x[s][2] - mctr[2], G.Lz)) - mhw[2], 0.0);
+      const double tmax = sqrt(fmax(1.0 - (dx * dx + dz * dz) / (R * R), 0.0)) + 1e-9;
+      thi = fmin(thi, tmax);
+      tlo = fmax(tlo, -tmax);
       l0 = max((int)floor((nl * (1.0 - thi) - 1.0) * 0.5) - 1, 0);
       const int l1 = min((int)ceil((nl * (1.0 - tlo) - 1.0) * 0.5) + 1, nl - 1);
       cnt = l1 >= l0 ? l1 - l0 + 1 : 0;
