@@ -164,6 +164,7 @@ __global__ __launch_bounds__(1024) void k_interp(
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
   const T tadt = (T)adt;
   const int nb2 = nb * nb;
+
   int lo[3][3];
   for (int c = 0; c < 3; ++c)
     for (int a = 0; a < 3; ++a) lo[c][a] = brick_lo(xp[a], G.R, G.inv_h, stagger(c, a)) - 1;
@@ -233,22 +234,26 @@ __global__ __launch_bounds__(1024) void k_interp(
     if (active) {
       for (int cc = 0; cc < nc; ++cc) {
         const int c = c0 + cc;
+        // the 27-point sum contracted separably (x, then y, then z)
         Stencil<T> S;
         make_stencil<T>(G, c, X, S);
-        int b[3];
-        for (int a = 0; a < 3; ++a) b[a] = min(max(S.ic[a] - 1 - lo[c][a], 0), nb - 3);
+        const int b0 = min(max(S.ic[0] - 1 - lo[c][0], 0), nb - 3);
+        const int b1 = min(max(S.ic[1] - 1 - lo[c][1], 0), nb - 3);
+        const int b2 = min(max(S.ic[2] - 1 - lo[c][2], 0), nb - 3);
         const T *bk = brick + cc * nb2 * P;
-        T sum = 0;
+        T zsum = 0;
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk)
+        for (int kk = 0; kk < 3; ++kk) {
+          T ysum = 0;
 #pragma unroll
           for (int jj = 0; jj < 3; ++jj) {
-            const T wzy = S.w[2][kk] * S.w[1][jj];
-            const T *row = bk + ((b[2] + kk) * nb + (b[1] + jj)) * P + b[0];
-#pragma unroll
-            for (int ii = 0; ii < 3; ++ii) sum += row[ii] * (wzy * S.w[0][ii]);
+            const T *row = bk + ((b2 + kk) * nb + (b1 + jj)) * P + b0;
+            const T xsum = row[0] * S.w[0][0] + row[1] * S.w[0][1] + row[2] * S.w[0][2];
+            ysum += S.w[1][jj] * xsum;
           }
-        U[c] = sum;
+          zsum += S.w[2][kk] * ysum;
+        }
+        U[c] = zsum;
       }
     }
   }
