@@ -68,8 +68,8 @@ hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl) {
 int brick_edge(double R, double h) { return (int)std::ceil(2.0 * R / h) + 5; }
 
 size_t brick_bytes(int nb, int esz) {
-  const int vec = 16 / esz;
-  return (size_t)nb * nb * ((nb + vec - 1) / vec * vec) * esz;
+  return (size_t)nb * nb * (esz == 8 ? brick_pitch_c<double>(nb) : brick_pitch_c<float>(nb)) *
+         esz;
 }
 
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }

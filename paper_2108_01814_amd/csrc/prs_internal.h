@@ -112,9 +112,16 @@ hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
 int brick_edge(double R, double h);
 // LDS bytes of one component's interpolation brick (x-rows padded to 16 bytes).
 size_t brick_bytes(int nb, int esz);
+// Row pitch of the brick in elements: nb rounded up to 16 bytes, plus
+// PRS_BRICK_PAD 16-byte vectors (a knob: padding by one or two vectors
+// measured slower at D/h = 10 on MI355X).
+#ifndef PRS_BRICK_PAD
+#define PRS_BRICK_PAD 0
+#endif
 template <typename T>
 __host__ __device__ constexpr int brick_pitch_c(int nb) {
-  return (nb + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T)) * (16 / (int)sizeof(T));
+  return ((nb + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T)) + PRS_BRICK_PAD) *
+         (16 / (int)sizeof(T));
 }
 template <typename T>
 hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, const T *gu,
