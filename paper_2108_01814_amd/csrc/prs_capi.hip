@@ -195,6 +195,12 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
   const T *fc[3] = {ff[0], ff[1], ff[2]};
   double *hist_host = c->host_pinned;
   bool den_ready = false;
+  // the first spreading pass of the step records each tile's culled markers,
+  // the later ones replay them (the spheres do not move during the forcing)
+  int spreads = 0;
+  auto tile_cache = [&]() {
+    return TileCache{spreads++ == 0 ? 1 : 2, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
+  };
   if (learned) {
     // features, zero-forcing slip and the prediction F0 -> dF in one pass
     LearnArgs la{};
@@ -206,7 +212,7 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
     HIP_TRY(c, launch_ib_begin(s, S, n));
     HIP_TRY(c, launch_ft_commit(s, S, n));
     HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr));
+    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr, tile_cache()));
     HIP_TRY(c, phase_end(c, s, kSpread));
     den_ready = true;
   } else {
@@ -220,7 +226,8 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
     if (F0) {
       HIP_TRY(c, launch_marker_sums<T>(s, c->G, S, n, (const T *)F0));
       HIP_TRY(c, phase_begin(c, s));
-      HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0));
+      HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0,
+                                        tile_cache()));
       HIP_TRY(c, phase_end(c, s, kSpread));
     } else {
       HIP_TRY(c, launch_ib_begin(s, S, n));
@@ -267,7 +274,7 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
     if (target) HIP_TRY(c, launch_accum_target<T>(s, c->G, S, n, adt, target));
     HIP_TRY(c, launch_ft_commit(s, S, n));
     HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr));
+    HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr, tile_cache()));
     HIP_TRY(c, phase_end(c, s, kSpread));
     iters = it + 1;
   }
@@ -421,6 +428,16 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   char *dF = nullptr;
   rc |= alloc(c, &dF, 3 * n * (size_t)q.n_markers * esz);
   S.dF = dF;
+  {
+    // record of the spreading's culled markers per grid tile, reused by the
+    // later passes of a step: 2048 markers and 256 candidate spheres per tile
+    // (a tile with more is culled again instead)
+    const int ntiles = esz == 8 ? spread_tile_count<double>(c->G) : spread_tile_count<float>(c->G);
+    S.tc_cap = 2048 + 256;
+    rc |= alloc(c, &S.tc_items, (size_t)ntiles * S.tc_cap);
+    rc |= alloc(c, &S.tc_count, (size_t)ntiles);
+    rc |= alloc(c, &S.tc_ncand, (size_t)ntiles);
+  }
   rc |= alloc(c, &S.status, 4);
   rc |= alloc(c, &S.counters, 4);
   rc |= alloc(c, &S.templ, 3 * (size_t)q.n_markers);

@@ -651,6 +651,58 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
   }
 }
 
+// Accumulator unit of a tile: fixed point (single-precision fields) takes
+// the smallest power of two >= B / 2^30 for the bound B on any node sum (a
+// power of two keeps the unit, and so the sums, independent of the order in
+// which B was summed); a non-finite bound poisons the tile.  Floating-point
+// accumulators (double-precision fields) use dV / h^3 as the scale.
+template <typename T, bool kFixed>
+__device__ inline void tile_unit(double bound, double dvh, double &unit, bool &poison, T &scale) {
+  unit = 1.0;
+  poison = false;
+  scale = (T)dvh;
+  if (!kFixed) return;
+  if (!(bound < INFINITY)) {
+    poison = true;
+    scale = (T)0;
+    return;
+  }
+  if (!(bound > 0.0)) {
+    scale = (T)0;   // every marker value is zero
+    return;
+  }
+  int ex;
+  frexp(bound * (1.0 / 1073741824.0), &ex);
+  unit = ldexp(1.0, ex);
+  scale = (T)(dvh / unit);
+}
+
+// Write-back of a tile: each node with a non-zero accumulator is added to the
+// field once (plain read-modify-write; the tile owns its nodes), by x-rows:
+// TX lanes per row, rows (component, z, y).  A poisoned tile makes every node
+// NaN and raises the status flag.
+template <typename T, typename A_t, int TX, int TY, int TZ, int PX>
+__device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0, int k0,
+                                  double unit, bool poison, T *f0, T *f1, T *f2,
+                                  uint32_t *status) {
+  constexpr bool kFixed = std::is_integral<A_t>::value;
+  static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
+  const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
+  for (int row = threadIdx.x / TX; row < 3 * TZ * TY; row += kTileThreads / TX) {
+    const A_t a = acc[row * PX + lx];
+    if ((a == (A_t)0 && !poison) || i >= G.nx) continue;
+    const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
+    const int lz = rz / TY, ly = rz - lz * TY;
+    const int j = j0 + ly, k = k0 + lz;
+    const int nyc = G.ny + (c == 1 ? 1 : 0);
+    if (j >= nyc || k >= G.nz) continue;
+    const size_t g = ((size_t)k * nyc + j) * G.nx + i;
+    T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
+    Fp[g] += poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
+  }
+  if (poison && threadIdx.x == 0) atomicOr(status, kFlagNonFinite);
+}
+
 // SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
 //        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
 //        sorted order read at perm[k].
@@ -658,7 +710,7 @@ template <typename T, int SRC>
 __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
     const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
-    const float *__restrict__ vmax, T *f0, T *f1, T *f2, uint32_t *status) {
+    const float *__restrict__ vmax, T *f0, T *f1, T *f2, uint32_t *status, TileCache tc) {
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
   constexpr int PX = TX + PRS_SPREAD_PAD, NODES_P = PX * TY * TZ;
   using A_t = typename TileAcc<T>::type;
@@ -694,6 +746,55 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
                           (k0 + 0.5 * (TZ - 0.5)) * h};
   const double mhw[3] = {(0.5 * TX + 1.25) * h + 1e-9 * h, (0.5 * TY + 1.25) * h + 1e-9 * h,
                          (0.5 * TZ + 1.25) * h + 1e-9 * h};
+
+  constexpr bool kFixed = std::is_integral<A_t>::value;
+  const double dvh = G.dV * G.inv_h * G.inv_h * G.inv_h;
+  const int nl = G.nl;
+  const size_t M = N * nl;
+  double vsum = 0.0;   // sum of the candidates' largest |marker value| (fixed point)
+  double unit = 1.0;   // fixed point: the accumulators' unit
+  bool poison = false;
+  T scale = (T)dvh;
+
+  // Replay: this step's earlier pass recorded the tile's candidates and
+  // culled markers (the spheres have not moved since).
+  const int cached = tc.mode == 2 ? tc.count[tile] : -1;   // uniform
+  if (cached >= 0) {
+    if (cached == 0) return;
+    const unsigned *reg = tc.items + (size_t)tile * tc.cap;
+    const int ncand = tc.ncand[tile];
+    for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
+      const int k = (int)reg[t];
+      c_idx[t] = k;
+      c_x[t][0] = xs[k];
+      c_x[t][1] = xs[N + k];
+      c_x[t][2] = xs[2 * N + k];
+    }
+    if (kFixed) {
+      __shared__ double r_wv[kTileThreads / 64];
+      double vs = 0.0;
+      for (int t = threadIdx.x; t < ncand; t += blockDim.x) vs += (double)vmax[reg[t]];
+      for (int off = 32; off > 0; off >>= 1) vs += __shfl_xor(vs, off);
+      if ((threadIdx.x & 63) == 0) r_wv[threadIdx.x >> 6] = vs;
+      __syncthreads();
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) vsum += r_wv[w];
+    }
+    tile_unit<T, kFixed>(G.wsum_bound * dvh * vsum, dvh, unit, poison, scale);
+    for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) acc[q] = (A_t)0;
+    __syncthreads();
+    const unsigned *itm = reg + ncand;
+    for (int it = threadIdx.x; it < cached; it += blockDim.x) {
+      const unsigned cd = itm[it];
+      const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
+      const int k = c_idx[sc];
+      const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
+                           c_x[sc][2] + R * templ[3 * l + 2]};
+      spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
+    }
+    __syncthreads();
+    tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, f0, f1, f2, status);
+    return;
+  }
 
   if (threadIdx.x == 0) {
     c_n = 0;
@@ -732,10 +833,24 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   }
   __syncthreads();
   int nc = c_n;
-  if (nc == 0) return;
+  const bool record = tc.mode == 1;
+  if (nc == 0) {
+    if (record && threadIdx.x == 0) tc.count[tile] = 0;
+    return;
+  }
   if (nc > kTileCand) {
     if (threadIdx.x == 0) atomicOr(status, kFlagCand);
     nc = kTileCand;
+  }
+  // recording: the candidates first, then the culled markers as
+  // (candidate slot << 10 | marker); a tile whose list does not fit is not
+  // recorded
+  unsigned *reg = record ? tc.items + (size_t)tile * tc.cap : nullptr;
+  __shared__ int r_len;   // entries recorded so far, -1 once out of room
+  if (record) {
+    if (threadIdx.x == 0) r_len = nc <= tc.cap ? nc : -1;
+    if (nc <= tc.cap)
+      for (int t = threadIdx.x; t < nc; t += blockDim.x) reg[t] = (unsigned)c_idx[t];
   }
   // markers of each sphere that can reach the tile: the template's
   // y-component 1 - (2l+1)/N_L is monotone in l, so the markers within the
@@ -743,7 +858,6 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   // outside the markers' reach box in x (z) needs |t_x| >= dx/R and |t_z| >=
   // dz/R, so t_x^2 + t_z^2 = 1 - t_y^2 >= (dx^2 + dz^2) / R^2: a band around
   // the equator, which narrows the range further.
-  const int nl = G.nl;
   const double ylo = (j0 - 1.5) * h, yhi = (j0 + TY + 1.0) * h;
   for (int s = threadIdx.x; s < kTileCand; s += blockDim.x) {
     int cnt = 0, l0 = 0;
@@ -766,8 +880,6 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads): shuffles inside each wave, then the wave
   // totals
-  constexpr bool kFixed = std::is_integral<A_t>::value;
-  double vsum = 0.0;   // sum of the candidates' largest |marker value| (fixed point)
   {
     __shared__ int c_wsum[kTileCand / 64];
     __shared__ double c_wvsum[kTileCand / 64];
@@ -796,14 +908,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     __syncthreads();
   }
   const int total = c_pref[kTileCand];
-  const double dvh = G.dV * G.inv_h * G.inv_h * G.inv_h;
-  // fixed point: unit = B / 2^30; a non-finite bound (non-finite marker
-  // values) poisons the tile's nodes instead
-  const double bound = G.wsum_bound * dvh * vsum;
-  const bool poison = kFixed && !(bound < INFINITY);
-  const double unit = kFixed ? bound * (1.0 / 1073741824.0) : 1.0;
-  const T scale = (T)(kFixed ? (unit > 0.0 && !poison ? dvh / unit : 0.0) : dvh);
-  const size_t M = N * nl;
+  tile_unit<T, kFixed>(G.wsum_bound * dvh * vsum, dvh, unit, poison, scale);
   // Rounds of blockDim items (sphere, marker) of the y-bands: cull each item
   // by the tile's reach box and append the survivors to an LDS list (wave
   // ballot + one LDS atomic per wave); once the list could overflow, or at
@@ -839,39 +944,33 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     const bool flush = listed > kTileList - (int)blockDim.x || base0 + (int)blockDim.x >= total;
     __syncthreads();   // every lane has read the count before the next round appends
     if (flush) {
+      const int rbase = record ? r_len : -1;
+      const bool keep = rbase >= 0 && rbase + listed <= tc.cap;
       for (int it = threadIdx.x; it < listed; it += blockDim.x) {
         const unsigned cd = c_list[it];
         const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
         const int k = c_idx[sc];
+        if (keep) reg[rbase + it] = cd;
         const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
                              c_x[sc][2] + R * templ[3 * l + 2]};
         spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
       }
       __syncthreads();
-      if (threadIdx.x == 0) c_list_n = 0;
+      if (threadIdx.x == 0) {
+        c_list_n = 0;
+        if (record) r_len = keep ? rbase + listed : -1;
+      }
       __syncthreads();
     }
   }
-  __syncthreads();
-  // write-back by x-rows: TX lanes per row, rows (component, z, y)
-  static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
-  {
-    const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
-    for (int row = threadIdx.x / TX; row < 3 * TZ * TY; row += kTileThreads / TX) {
-      const A_t a = acc[row * PX + lx];
-      if ((a == (A_t)0 && !poison) || i >= G.nx) continue;
-      const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
-      const int lz = rz / TY, ly = rz - lz * TY;
-      const int j = j0 + ly, k = k0 + lz;
-      const int nyc = G.ny + (c == 1 ? 1 : 0);
-      if (j >= nyc || k >= G.nz) continue;
-      const size_t g = ((size_t)k * nyc + j) * G.nx + i;
-      T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
-      Fp[g] += poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
-    }
+  if (record && threadIdx.x == 0) {
+    tc.count[tile] = r_len >= 0 ? r_len - nc : -1;
+    tc.ncand[tile] = nc;
   }
-  if (poison && threadIdx.x == 0) atomicOr(status, kFlagNonFinite);
+  __syncthreads();
+  tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, f0, f1, f2, status);
 }
+
 
 // vmax[p] = largest |component| of the caller-ordered marker values of
 // sorted sphere p (NaN if any is NaN).
@@ -910,11 +1009,10 @@ template hipError_t launch_sphere_vmax<double>(hipStream_t, const Geom &, const 
 
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
-                               T *f[3], int n, const T *src_caller) {
+                               T *f[3], int n, const T *src_caller, TileCache tc) {
   if (n == 0) return hipSuccess;
-  constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
-  const int ntiles =
-      ((G.nx + TX - 1) / TX) * ((G.ny + 1 + TY - 1) / TY) * ((G.nz + TZ - 1) / TZ);
+  const int ntiles = spread_tile_count<T>(G);
+  if (!tc.items) tc.mode = 0;
   // caller values: their per-sphere maxima first (the correction buffer's are
   // written by the interpolation pass that fills it)
   if (src_caller) {
@@ -922,20 +1020,29 @@ hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_spread_tiles<T, 1>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
                        G, C, S.start, S.xs[0], n, S.templ, src_caller, S.perm, S.vmax, f[0],
-                       f[1], f[2], S.status);
+                       f[1], f[2], S.status, tc);
   } else {
     hipLaunchKernelGGL((k_spread_tiles<T, 0>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
                        G, C, S.start, S.xs[0], n, S.templ, (const T *)S.dF, S.perm, S.vmax, f[0],
-                       f[1], f[2], S.status);
+                       f[1], f[2], S.status, tc);
   }
   return hipGetLastError();
 }
 
+template <typename T>
+int spread_tile_count(const Geom &G) {
+  constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
+  return ((G.nx + TX - 1) / TX) * ((G.ny + 1 + TY - 1) / TY) * ((G.nz + TZ - 1) / TZ);
+}
+template int spread_tile_count<float>(const Geom &);
+template int spread_tile_count<double>(const Geom &);
+
 template hipError_t launch_spread_tiles<float>(hipStream_t, const Geom &, const Cells &,
-                                               const Scratch &, float *[3], int, const float *);
+                                               const Scratch &, float *[3], int, const float *,
+                                               TileCache);
 template hipError_t launch_spread_tiles<double>(hipStream_t, const Geom &, const Cells &,
                                                 const Scratch &, double *[3], int,
-                                                const double *);
+                                                const double *, TileCache);
 
 // ---------------------------------------------------------------------------
 // per-sphere force/torque bookkeeping

@@ -70,6 +70,10 @@ struct Scratch {
   double *ft_part;            // [12][n]: the same for the latest interpolation pass
   double *slip_part;          // [2][n]: slip^2 and zero-forcing slip^2 per sphere
   float *vmax;                // [n]: largest |marker value| per sphere (latest spread source)
+  // per-tile record of the spreading (TileCache)
+  unsigned *tc_items;
+  int *tc_count, *tc_ncand;
+  int tc_cap;
   double *slip_hist;          // [kMaxSlip + 1 + 256]: per pass, zero-forcing, block partials
   int *ncand, *cand;          // [n], [kCandCap][n]
   // contact history, internal SoA layout [slot][n], double-buffered
@@ -94,6 +98,20 @@ struct LearnArgs {
   const float *norm;           // feature mean/std, target mean/std
   float *feat;                 // feature pass: [n][nl][16] in caller order
   const int *perm;             // sorted position -> caller index
+};
+
+// Per-tile record of the spreading's candidate spheres and culled markers,
+// reused by the later passes of a step (the spheres do not move between
+// them).  Tile t's region items[t * cap ...]: ncand[t] sorted sphere indices,
+// then count[t] markers as (candidate slot << 10 | marker); count -1: not
+// recorded.
+// mode 0: neither record nor replay; 1: record; 2: replay recorded tiles.
+struct TileCache {
+  int mode;
+  int cap;
+  unsigned *items;
+  int *count;
+  int *ncand;
 };
 
 // ---- launchers (defined in the .hip files) ----
@@ -146,7 +164,10 @@ void mlp_buffers(const prs_mlp *mlp, LearnArgs *la);
 
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
-                               T *f[3], int n, const T *src_caller);
+                               T *f[3], int n, const T *src_caller, TileCache tc = TileCache{});
+// Tiles of the spreading grid for fields of type T.
+template <typename T>
+int spread_tile_count(const Geom &G);
 hipError_t launch_ft_commit(hipStream_t s, const Scratch &S, int n);
 template <typename T>
 hipError_t launch_sphere_vmax(hipStream_t s, const Geom &G, const Scratch &S, int n, const T *F);
