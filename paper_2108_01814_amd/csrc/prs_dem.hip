@@ -250,19 +250,14 @@ __global__ __launch_bounds__(256) void k_substep(
     if (!(xp[1] >= 0.0 && xp[1] <= G.Ly)) fl |= kFlagDomain;
     if (fl) atomicOr(status, fl);
   }
-  // contact counters: one atomic per wave
-  unsigned long long c0 = (unsigned long long)(my_pp + my_wall);
-  unsigned long long c1 = (unsigned long long)my_pp, c2 = (unsigned long long)my_wall;
-  for (int off = 32; off > 0; off >>= 1) {
-    c0 += __shfl_xor(c0, off);
-    c1 += __shfl_xor(c1, off);
-    c2 += __shfl_xor(c2, off);
-  }
-  if ((threadIdx.x & 63) == 0) {
+  // contact counters: one atomic per wave (a wave's counts fit in 32 bits)
+  const int c1 = wave_sum_last(my_pp), c2 = wave_sum_last(my_wall);
+  if ((threadIdx.x & 63) == 63) {
+    const unsigned long long c0 = (unsigned long long)c1 + (unsigned long long)c2;
     if (c0) atomicAdd(&counters[0], c0);
     if (last) {
-      if (c1) atomicAdd(&counters[1], c1);
-      if (c2) atomicAdd(&counters[2], c2);
+      if (c1) atomicAdd(&counters[1], (unsigned long long)c1);
+      if (c2) atomicAdd(&counters[2], (unsigned long long)c2);
     }
   }
 }

@@ -34,6 +34,60 @@ __device__ inline void comp_add(double &s, double &c, double s2, double c2) {
 // max(a, b) that keeps a NaN of either argument.
 __device__ inline float nan_max(float a, float b) { return (b > a || b != b) ? b : a; }
 
+// ---- wave reductions on DPP lane moves (VALU only, no LDS traffic) -------
+// A DPP move reads another lane of the same wave; rows are 16 lanes.  Lanes
+// of rows outside ROW_MASK receive 0.  Every lane of the wave must be active.
+enum : int {
+  kDppXor1 = 0xB1,          // quad_perm [1,0,3,2]
+  kDppXor2 = 0x4E,          // quad_perm [2,3,0,1]
+  kDppHalfMirror = 0x141,   // lane i <- 7 - i within each 8 lanes
+  kDppMirror = 0x140,       // lane i <- 15 - i within each row
+  kDppBcast15 = 0x142,      // lane 15 of each row -> the next row
+  kDppBcast31 = 0x143,      // lane 31 -> rows 2 and 3
+};
+
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Sum over the wave, valid in lane 63: butterflies inside each quad, mirrors
+// fold quads into rows, row broadcasts fold rows 0..2 into row 3.
+template <typename T>
+__device__ inline T wave_sum_last(T v) {
+  v += dpp_move<kDppXor1, 0xF>(v);
+  v += dpp_move<kDppXor2, 0xF>(v);
+  v += dpp_move<kDppHalfMirror, 0xF>(v);
+  v += dpp_move<kDppMirror, 0xF>(v);
+  v += dpp_move<kDppBcast15, 0xA>(v);
+  v += dpp_move<kDppBcast31, 0xC>(v);
+  return v;
+}
+
+// nan_max over the wave of non-negative values (or NaN), valid in lane 63.
+__device__ inline float wave_nanmax_last(float v) {
+  v = nan_max(v, dpp_move<kDppXor1, 0xF>(v));
+  v = nan_max(v, dpp_move<kDppXor2, 0xF>(v));
+  v = nan_max(v, dpp_move<kDppHalfMirror, 0xF>(v));
+  v = nan_max(v, dpp_move<kDppMirror, 0xF>(v));
+  v = nan_max(v, dpp_move<kDppBcast15, 0xA>(v));
+  v = nan_max(v, dpp_move<kDppBcast31, 0xC>(v));
+  return v;
+}
+
 __device__ inline int wrap_once(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }

@@ -344,37 +344,38 @@ __global__ __launch_bounds__(1024) void k_interp(
         out[c * M + m] = corr;
         vm = nan_max(vm, fabsf((float)corr));
         d[c] = (double)corr;
-        red.q[0] += (double)res * (double)res;
+        red.v[kColSlip] += (double)res * (double)res;
       }
       red_set_ft(red, rl, d);
     } else {
       for (int c = 0; c < 3; ++c) {
         const double z = Ud[c] - (double)U[c];
-        red.q[1] += z * z;
+        red.v[kColSlip0] += z * z;
       }
     }
   }
   __shared__ float s_vmax[16];
-  if (MODE == kInterpMDF || MODE == kInterpLearned) {
-    for (int off = 32; off > 0; off >>= 1) vm = nan_max(vm, __shfl_xor(vm, off));
-    if ((threadIdx.x & 63) == 0) s_vmax[threadIdx.x >> 6] = vm;
+  constexpr bool kForce = MODE == kInterpMDF || MODE == kInterpLearned;
+  if (kForce) {
+    vm = wave_nanmax_last(vm);
+    if ((threadIdx.x & 63) == 63) s_vmax[threadIdx.x >> 6] = vm;
   }
-  block_reduce(red);   // (its barrier also publishes s_vmax)
-  if (threadIdx.x == 0) {
-    if ((MODE == kInterpMDF || MODE == kInterpLearned) && vmax_out) {
-      float m = 0.f;
-      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) m = nan_max(m, s_vmax[wv]);
-      vmax_out[p] = m;
-    }
-    if (MODE == kInterpMDF || MODE == kInterpLearned) {
-      if (MODE == kInterpMDF) slip_part[p] = red.q[0];
-      for (int k = 0; k < 6; ++k) {
-        ft_part[(2 * k) * N + p] = red.s[k];
-        ft_part[(2 * k + 1) * N + p] = red.c[k];
-      }
-    }
-    if (MODE != kInterpMDF) slip_part[N + p] = red.q[1];
+  constexpr unsigned kMask = (kForce ? 0x3Fu : 0u) |
+                             (MODE == kInterpMDF ? 1u << kColSlip : 1u << kColSlip0);
+  double rs, rc;
+  block_reduce<kMask>(red, rs, rc);   // (its barrier also publishes s_vmax)
+  const int t = threadIdx.x;
+  if (kForce && t == 0 && vmax_out) {
+    float m = 0.f;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) m = nan_max(m, s_vmax[wv]);
+    vmax_out[p] = m;
   }
+  if (kForce && t < 6) {
+    ft_part[(2 * t) * N + p] = rs;
+    ft_part[(2 * t + 1) * N + p] = rc;
+  }
+  if (MODE == kInterpMDF && t == kColSlip) slip_part[p] = rs;
+  if (MODE != kInterpMDF && t == kColSlip0) slip_part[N + p] = rs;
 }
 
 // Launch k_interp with the brick edge as a compile-time constant when it is
@@ -774,8 +775,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
       __shared__ double r_wv[kTileThreads / 64];
       double vs = 0.0;
       for (int t = threadIdx.x; t < ncand; t += blockDim.x) vs += (double)vmax[reg[t]];
-      for (int off = 32; off > 0; off >>= 1) vs += __shfl_xor(vs, off);
-      if ((threadIdx.x & 63) == 0) r_wv[threadIdx.x >> 6] = vs;
+      vs = wave_sum_last(vs);
+      if ((threadIdx.x & 63) == 63) r_wv[threadIdx.x >> 6] = vs;
       __syncthreads();
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) vsum += r_wv[w];
     }
@@ -893,8 +894,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
     if (t < kTileCand && ln == 63) c_wsum[t >> 6] = incl;
     if (kFixed) {
       double vs = t < nc ? (double)vmax[c_idx[t]] : 0.0;
-      for (int off = 32; off > 0; off >>= 1) vs += __shfl_xor(vs, off);
-      if (t < kTileCand && ln == 0) c_wvsum[t >> 6] = vs;
+      vs = wave_sum_last(vs);
+      if (t < kTileCand && ln == 63) c_wvsum[t >> 6] = vs;
     }
     __syncthreads();
     if (kFixed)
@@ -986,10 +987,11 @@ __global__ __launch_bounds__(1024) void k_sphere_vmax(Geom G, const T *__restric
     const size_t q = ((size_t)perm[p] * G.nl + threadIdx.x) * 3;
     for (int c = 0; c < 3; ++c) m = nan_max(m, fabsf((float)F[q + c]));
   }
-  for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  m = wave_nanmax_last(m);
+  if ((threadIdx.x & 63) == 63) wm[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
+    m = wm[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = nan_max(m, wm[w]);
     vmax[p] = m;
   }
@@ -1077,19 +1079,19 @@ __global__ __launch_bounds__(1024) void k_marker_sums(Geom G, const double *__re
   const int l = threadIdx.x;
   Red red;
   red_zero(red);
-  float vm = 0.f;   // largest |value| this lane writes to out (MDF, learned)
   if (l < G.nl) {
     const double rl[3] = {G.R * templ[3 * l], G.R * templ[3 * l + 1], G.R * templ[3 * l + 2]};
     const size_t m = (size_t)perm[p] * G.nl + l;
     const double d[3] = {(double)F0[3 * m], (double)F0[3 * m + 1], (double)F0[3 * m + 2]};
     red_set_ft(red, rl, d);
   }
-  block_reduce(red);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 6; ++k) {
-      acc[(2 * k) * (size_t)n + p] = red.s[k];
-      acc[(2 * k + 1) * (size_t)n + p] = red.c[k];
-    }
+  double rs, rc;
+  block_reduce<0x3Fu>(red, rs, rc);
+  const int t = threadIdx.x;
+  if (t < 6) {
+    acc[(2 * t) * (size_t)n + p] = rs;
+    acc[(2 * t + 1) * (size_t)n + p] = rc;
+  }
 }
 
 template <typename T>

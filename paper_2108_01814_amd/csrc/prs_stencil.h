@@ -45,60 +45,50 @@ __device__ inline int brick_lo(double xc, double R, double inv_h, double o) {
 }
 
 // ---- per-sphere block reductions -----------------------------------------
-// 6 compensated pairs (force and torque sums) + 2 plain sums.
+// Eight columns per lane: the force and torque terms (0..5) and two slip
+// sums (6: with forcing, 7: zero forcing).
+enum { kColF = 0, kColSlip = 6, kColSlip0 = 7 };
 struct Red {
-  double s[6], c[6];
-  double q[2];
+  double v[8];
 };
 
 __device__ inline void red_zero(Red &r) {
-  for (int k = 0; k < 6; ++k) r.s[k] = r.c[k] = 0.0;
-  r.q[0] = r.q[1] = 0.0;
+  for (int k = 0; k < 8; ++k) r.v[k] = 0.0;
 }
 
 __device__ inline void red_set_ft(Red &r, const double rl[3], const double d[3]) {
-  r.s[0] = d[0];
-  r.s[1] = d[1];
-  r.s[2] = d[2];
-  r.s[3] = rl[1] * d[2] - rl[2] * d[1];
-  r.s[4] = rl[2] * d[0] - rl[0] * d[2];
-  r.s[5] = rl[0] * d[1] - rl[1] * d[0];
+  r.v[0] = d[0];
+  r.v[1] = d[1];
+  r.v[2] = d[2];
+  r.v[3] = rl[1] * d[2] - rl[2] * d[1];
+  r.v[4] = rl[2] * d[0] - rl[0] * d[2];
+  r.v[5] = rl[0] * d[1] - rl[1] * d[0];
 }
 
-// Inside a wave a plain FP64 butterfly (at most 6 roundings per term, far
-// below the single-precision inputs' own error); the compensated sums start
-// at the cross-wave level.
-__device__ inline void wave_reduce(Red &r) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) r.s[k] += __shfl_xor(r.s[k], off);
-    r.q[0] += __shfl_xor(r.q[0], off);
-    r.q[1] += __shfl_xor(r.q[1], off);
-  }
-}
-
-// Result valid in thread 0.  All threads of the block must call it.
-__device__ inline void block_reduce(Red &r) {
-  __shared__ double lds[16][14];
+// Block sums of the columns in MASK: a plain FP64 sum inside each wave (at
+// most 6 roundings per term, far below the single-precision inputs' own
+// error), compensated across waves.  On return thread t < 8 holds column t's
+// sum as a compensated pair (s, c); other threads get zeros.  All threads of
+// the block must call it; blockDim.x is a multiple of 64.
+template <unsigned MASK>
+__device__ inline void block_reduce(Red &r, double &s, double &c) {
+  __shared__ double lds[16][8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  wave_reduce(r);
-  if (lane == 0) {
-    for (int k = 0; k < 6; ++k) {
-      lds[wave][k] = r.s[k];
-      lds[wave][6 + k] = r.c[k];
-    }
-    lds[wave][12] = r.q[0];
-    lds[wave][13] = r.q[1];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if ((MASK >> k) & 1u) r.v[k] = wave_sum_last(r.v[k]);
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if ((MASK >> k) & 1u) lds[wave][k] = r.v[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int wv = 1; wv < nw; ++wv) {
-      for (int k = 0; k < 6; ++k) comp_add(r.s[k], r.c[k], lds[wv][k], lds[wv][6 + k]);
-      r.q[0] += lds[wv][12];
-      r.q[1] += lds[wv][13];
-    }
+  s = c = 0.0;
+  const int t = threadIdx.x;
+  if (t < 8 && ((MASK >> t) & 1u)) {
+    s = lds[0][t];
+    for (int wv = 1; wv < nw; ++wv) comp_add(s, c, lds[wv][t], 0.0);
   }
 }
 
