@@ -56,21 +56,21 @@ def touched_nodes(ctx, x, torch):
     return out
 
 
-def ib_bytes(w, n_touched, s, iters):
-    """Algorithmic bytes of one interpolation and one spreading pass (averages
-    over the step's passes).
+def ib_bytes(w, n_touched, s):
+    """Algorithmic bytes of one interpolation and one spreading pass (the
+    same for every pass of the step).
 
-    interpolation: read u-hat and f at every touched node (2 s per node and
-    component; the first pass after clearing f reads u-hat only, so the
-    average over `iters` passes is (2 iters - 1) s / iters), write the marker
-    correction (3 s per marker), read the sphere state (9 doubles) and write
-    the slip partials (2 doubles) per sphere.
+    interpolation: read one field at every touched node (s per node and
+    component: u-hat in the first pass, f in the later ones), write (first
+    pass) or read (later passes) the markers' interpolated u-hat (3 s per
+    marker), write the marker correction (3 s per marker), read the sphere
+    state (9 doubles) and write the slip partials (2 doubles) per sphere.
     spreading: read the correction (3 s per marker), read-modify-write f at
     every touched node (2 s), read-modify-write the 12 force/torque
     accumulators per sphere."""
     M = w.n * w.n_markers
     NT = sum(n_touched)
-    interp = NT * s * (2 * iters - 1) / iters + M * 3 * s + w.n * (9 + 2) * 8
+    interp = NT * s + M * 3 * s * 2 + w.n * (9 + 2) * 8
     spread = M * 3 * s + NT * 2 * s + w.n * 3 * 8 + w.n * 12 * 8 * 2
     return interp, spread
 
@@ -373,7 +373,7 @@ def main(argv=None):
     iters = r32["stats"]["iterations"]
     t_ib = (tm["ms_interp"] + tm["ms_spread"]) / 1e3 / K
     t_dem = (tm["ms_search"] + tm["ms_substep"]) / 1e3 / K
-    b_interp, b_spread = ib_bytes(w, r32["touched"], 4, iters)
+    b_interp, b_spread = ib_bytes(w, r32["touched"], 4)
     avg_interp = tm["ms_interp"] / max(tm["n_interp"], 1)
     avg_spread = tm["ms_spread"] / max(tm["n_spread"], 1)
     kern = {"prs::k_interp<float, 0, false, 15>": (b_interp, avg_interp),

@@ -428,6 +428,9 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   char *dF = nullptr;
   rc |= alloc(c, &dF, 3 * n * (size_t)q.n_markers * esz);
   S.dF = dF;
+  char *u0 = nullptr;
+  rc |= alloc(c, &u0, 3 * n * (size_t)q.n_markers * esz);
+  S.u0 = u0;
   {
     // record of the spreading's culled markers per grid tile, reused by the
     // later passes of a step: 2048 markers and 256 candidate spheres per tile

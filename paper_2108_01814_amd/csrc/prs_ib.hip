@@ -125,7 +125,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
     double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la,
-    float *__restrict__ vmax_out) {
+    float *__restrict__ vmax_out, T *__restrict__ u0) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *brick = reinterpret_cast<T *>(smem_raw);
   if (NB > 0) nb = NB;
@@ -164,6 +164,11 @@ __global__ __launch_bounds__(1024) void k_interp(
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
   const T tadt = (T)adt;
   const int nb2 = nb * nb;
+  // An MDF pass over a nonzero f interpolates f alone and adds the step's
+  // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
+  // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
+  // that interpolate u-hat record it in u0.
+  const bool f_only = MODE == kInterpMDF && b0 != nullptr;
 
   int lo[3][3];
   for (int c = 0; c < 3; ++c)
@@ -200,23 +205,13 @@ __global__ __launch_bounds__(1024) void k_interp(
             const int k = wrap_once(lo[c][2] + bz, G.nz);
             const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
             const int x0 = lo[c][0] + ch * VEC;
-            const T *Ap = (c == 0 ? a0 : (c == 1 ? a1 : a2)) + rowg;
-            const T *Bp = (c == 0 ? b0 : (c == 1 ? b1 : b2)) + rowg;
+            const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
+                                  : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
             if (x0 >= 0 && x0 + VEC <= G.nx) {
-              __builtin_memcpy(&v[u], Ap + x0, sizeof(vec_t));
-              if (MODE == kInterpMDF && b0) {
-                vec_t bv;
-                __builtin_memcpy(&bv, Bp + x0, sizeof(vec_t));
-                v[u] += tadt * bv;
-              }
+              __builtin_memcpy(&v[u], Sp + x0, sizeof(vec_t));
             } else {
 #pragma unroll
-              for (int e = 0; e < VEC; ++e) {
-                const int i = wrap_once(x0 + e, G.nx);
-                T a = Ap[i];
-                if (MODE == kInterpMDF && b0) a += tadt * Bp[i];
-                v[u][e] = a;
-              }
+              for (int e = 0; e < VEC; ++e) v[u][e] = Sp[wrap_once(x0 + e, G.nx)];
             }
           }
         }
@@ -256,6 +251,14 @@ __global__ __launch_bounds__(1024) void k_interp(
         U[c] = zsum;
       }
     }
+  }
+
+  if (MODE != kInterpPlain && active && u0) {
+    const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
+    if (f_only)
+      for (int c = 0; c < 3; ++c) U[c] = u0[c * M + m] + tadt * U[c];
+    else
+      for (int c = 0; c < 3; ++c) u0[c * M + m] = U[c];
   }
 
   if (MODE == kInterpPlain) {
@@ -386,19 +389,19 @@ void launch_interp_nb(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Ge
                       const T *b1, const T *b2, double adt, const double *xs, const double *us,
                       const double *ws, int n, int nb, T *out, T *out2, double *slip_part,
                       double *ft_part, const int *order, const LearnArgs &la,
-                      float *vmax_out) {
+                      float *vmax_out, T *u0) {
   if (nb == 15)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 15>), grid, block, lds, s, G, templ, a0, a1, a2,
                        b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out);
+                       vmax_out, u0);
   else if (nb == 21)
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 21>), grid, block, lds, s, G, templ, a0, a1, a2,
                        b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out);
+                       vmax_out, u0);
   else
     hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 0>), grid, block, lds, s, G, templ, a0, a1, a2,
                        b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out);
+                       vmax_out, u0);
 }
 
 template <typename T, int MODE>
@@ -407,7 +410,7 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
                              double adt, const double *xs, const double *us, const double *ws,
                              int n, T *out, T *out2, double *slip_part, double *ft_part,
                              const int *order, const LearnArgs &la = LearnArgs{},
-                             float *vmax_out = nullptr) {
+                             float *vmax_out = nullptr, T *u0 = nullptr) {
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
   const size_t one = sizeof(T) * nb * nb * brick_pitch_c<T>(nb);
@@ -417,10 +420,12 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, 
   if (MODE == kInterpLearned) lds = std::max(lds, learned_lds_bytes(G.nl));
   if (all3)
     launch_interp_nb<T, MODE, true>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out);
+                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out,
+                                    u0);
   else
     launch_interp_nb<T, MODE, false>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out);
+                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out,
+                                    u0);
   return hipGetLastError();
 }
 
@@ -439,11 +444,12 @@ hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, con
   if (den_only)
     return launch_interp_any<T, kInterpDen>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
                                             nullptr, adt, S.xs[0], S.us[0], S.ws[0], n, nullptr,
-                                            nullptr, S.slip_part, nullptr, S.lane_order);
+                                            nullptr, S.slip_part, nullptr, S.lane_order,
+                                            LearnArgs{}, nullptr, (T *)S.u0);
   return launch_interp_any<T, kInterpMDF>(s, G, S.templ, uh[0], uh[1], uh[2], f[0], f[1], f[2],
                                           adt, S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
                                           S.slip_part, S.ft_part, S.lane_order, LearnArgs{},
-                                          S.vmax);
+                                          S.vmax, (T *)S.u0);
 }
 
 template <typename T>
@@ -463,7 +469,7 @@ hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S,
   return launch_interp_any<T, kInterpLearned>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
                                               nullptr, adt, S.xs[0], S.us[0], S.ws[0], n,
                                               (T *)S.dF, nullptr, S.slip_part, S.ft_part,
-                                              S.lane_order, la, S.vmax);
+                                              S.lane_order, la, S.vmax, (T *)S.u0);
 }
 
 // target[caller marker][c] += adt * dF[c][sorted marker]
@@ -707,8 +713,17 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
 // SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
 //        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
 //        sorted order read at perm[k].
+// Waves per SIMD the spreading kernel is compiled for: three 512-thread
+// tiles per compute unit in single precision (at most 80 VGPRs; one more
+// register drops the kernel to two tiles per CU and costs about 30 %).
+template <typename T>
+struct TileWaves {
+  static constexpr int value = sizeof(T) == 4 ? 3 * kTileThreads / 256 : 1;
+};
+
 template <typename T, int SRC>
-__global__ __launch_bounds__(kTileThreads) void k_spread_tiles(
+__global__ __launch_bounds__(kTileThreads)
+__attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
     const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
     const float *__restrict__ vmax, T *f0, T *f1, T *f2, uint32_t *status, TileCache tc) {

@@ -83,6 +83,8 @@ struct Scratch {
   int *ccount, *coffset;
   // marker corrections dF [3][n*nl] in grid precision
   void *dF;
+  // I[u-hat] of the step's markers [3][n*nl] in grid precision
+  void *u0;
   // status and counters
   uint32_t *status;
   unsigned long long *counters;   // [0] directed contacts, [1] pp last, [2] wall last
