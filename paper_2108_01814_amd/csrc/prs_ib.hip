@@ -100,12 +100,13 @@ enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2, kInterpFeat = 3, kInter
 // MODE kInterpPlain: caller-order AoS positions; a only; writes U [n][nl][3]
 //                    and optionally U_d.
 // Brick rows loaded per lane before the LDS stores (measured on MI355X at
-// D/h = 10: 2 is best for single precision, 4 for double).
+// D/h = 10 with one field per pass: 1 is best for single precision (2: +5 %,
+// 4: +15 %), 2 for double (1 and 4: +7 %)).
 #ifndef PRS_BRICK_UNROLL_F32
-#define PRS_BRICK_UNROLL_F32 2
+#define PRS_BRICK_UNROLL_F32 1
 #endif
 #ifndef PRS_BRICK_UNROLL_F64
-#define PRS_BRICK_UNROLL_F64 4
+#define PRS_BRICK_UNROLL_F64 2
 #endif
 #ifndef PRS_BRICK_ALL3_MAX_BYTES
 #define PRS_BRICK_ALL3_MAX_BYTES 0
