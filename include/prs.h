@@ -141,8 +141,9 @@ int prs_interpolate(prs_ctx *ctx, void *stream, const void *gu, const void *gv, 
 
 /* Diffusion / spreading (sec. 3.3), the adjoint of prs_interpolate:
  * f_c[node] += F_c * weight * dV / h^3 for every marker.  F: [n][n_markers][3];
- * fu, fv, fw: grid fields, accumulated into (accumulate != 0) or cleared
- * first (accumulate == 0).  FP64 fields accumulate with floating-point atomic
+ * fu, fv, fw: grid fields, accumulated into (accumulate != 0) or
+ * overwritten (accumulate == 0: every node stored, the entry values never
+ * read).  FP64 fields accumulate with floating-point atomic
  * adds, so the summation order (and the last bits) may differ between runs;
  * FP32 fields accumulate in 32-bit fixed point per tile of the grid (each
  * addend rounded to 2^-30 of a bound on the tile's node sums), which is
@@ -171,7 +172,9 @@ int prs_contacts(prs_ctx *ctx, void *stream, const double *x, int32_t n, int32_t
  *
  *   uhat  : 3 grid fields, the predicted fluid velocity u-hat (read only).
  *   f     : 3 grid fields, in/out.  On entry the initial forcing field
- *           (normally all zero; pass zero_f = 1 to have the call clear it);
+ *           (normally all zero; pass zero_f = 1 to have the call clear it:
+ *           the entry values are then never read, whatever they hold, and
+ *           the first spreading pass stores every node);
  *           on return the immersed-boundary force field.  The intermediate
  *           velocity of eq. 4 is u-tilde = u-hat + alpha dt_f f; it is never
  *           stored by the library.

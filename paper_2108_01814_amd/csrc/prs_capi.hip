@@ -186,7 +186,7 @@ int clear_field(prs_ctx *c, hipStream_t s, void *const f[3]) {
 template <typename T>
 int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *const f[3], int n,
                 const void *F0, bool need_den, bool learned, int n_fixed, float *target,
-                int &iters, int &n_slip, int &rejected) {
+                int &iters, int &n_slip, int &rejected, bool clear_f = false) {
   Scratch &S = c->S;
   const prs_params &q = c->p;
   const double adt = q.alpha * q.dt_f;
@@ -198,8 +198,14 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
   // the first spreading pass of the step records each tile's culled markers,
   // the later ones replay them (the spheres do not move during the forcing)
   int spreads = 0;
+  // clear_f: f is to be cleared; nothing reads it before the first spreading
+  // pass, which overwrites every node instead of adding
+  bool pending_clear = clear_f;
   auto tile_cache = [&]() {
-    return TileCache{spreads++ == 0 ? 1 : 2, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
+    TileCache tc{spreads++ == 0 ? 1 : 2, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
+    tc.overwrite = pending_clear ? 1 : 0;
+    pending_clear = false;
+    return tc;
   };
   if (learned) {
     // features, zero-forcing slip and the prediction F0 -> dF in one pass
@@ -277,6 +283,12 @@ int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *cons
     HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr, tile_cache()));
     HIP_TRY(c, phase_end(c, s, kSpread));
     iters = it + 1;
+  }
+  if (pending_clear) {
+    // no spreading pass ran (zero iterations, or the tolerance met at once)
+    HIP_TRY(c, phase_begin(c, s));
+    if (int rc = clear_field<T>(c, s, f)) return rc;
+    HIP_TRY(c, phase_end(c, s, kZeroF));
   }
   return PRS_OK;
 }
@@ -516,24 +528,23 @@ int prs_spread(prs_ctx *c, void *stream, const double *x, int32_t n, const void 
   void *g[3] = {fu, fv, fw};
   Scratch &S = c->S;
   HIP_TRY(c, launch_reset_status(s, S));
-  if (c->p.precision == PRS_F64) {
+  if (n == 0) {
+    // nothing to spread: accumulate leaves the field, otherwise it is cleared
     if (!accumulate)
-      for (int k = 0; k < 3; ++k)
-        HIP_TRY(c, launch_fill_zero<double>(s, (double *)g[k], grid_count(c, k)));
-  } else {
-    if (!accumulate)
-      for (int k = 0; k < 3; ++k)
-        HIP_TRY(c, launch_fill_zero<float>(s, (float *)g[k], grid_count(c, k)));
+      return c->p.precision == PRS_F64 ? clear_field<double>(c, s, g) : clear_field<float>(c, s, g);
+    return PRS_OK;
   }
-  if (n == 0) return PRS_OK;
   HIP_TRY(c, launch_sort(s, S, c->C_step, c->G, x, n, 0));
   HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n, nullptr, nullptr));
+  // without accumulate the pass overwrites every node (the field is not read)
+  TileCache tc{0, 0, nullptr, nullptr, nullptr};
+  tc.overwrite = accumulate ? 0 : 1;
   if (c->p.precision == PRS_F64)
     HIP_TRY(c, launch_spread_tiles<double>(s, c->G, c->C_step, S, (double **)g, n,
-                                           (const double *)F));
+                                           (const double *)F, tc));
   else
     HIP_TRY(c, launch_spread_tiles<float>(s, c->G, c->C_step, S, (float **)g, n,
-                                          (const float *)F));
+                                          (const float *)F, tc));
   return PRS_OK;
 }
 
@@ -587,14 +598,10 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
   HIP_TRY(c, launch_reset_status(s, S));
   c->marks.clear();
   c->events_used = 0;
-  if (zero_f) {
+  if (zero_f && n == 0) {
+    // (with spheres the forcing's first spreading pass overwrites f)
     HIP_TRY(c, phase_begin(c, s));
-    for (int k = 0; k < 3; ++k) {
-      if (f64)
-        HIP_TRY(c, launch_fill_zero<double>(s, (double *)f[k], grid_count(c, k)));
-      else
-        HIP_TRY(c, launch_fill_zero<float>(s, (float *)f[k], grid_count(c, k)));
-    }
+    if (int rc = f64 ? clear_field<double>(c, s, f) : clear_field<float>(c, s, f)) return rc;
     HIP_TRY(c, phase_end(c, s, kZeroF));
   }
   if (n > 0) {
@@ -615,9 +622,9 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
     const bool learned = c->mlp != nullptr;
     const int rc =
         f64 ? run_forcing<double>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
-                                  n_slip, rejected)
+                                  n_slip, rejected, zero_f != 0)
             : run_forcing<float>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
-                                 n_slip, rejected);
+                                 n_slip, rejected, zero_f != 0);
     if (rc != PRS_OK) return rc;
     HIP_TRY(c, launch_ib_finish(s, S, c->G, n, q.rho_f));
 

@@ -689,16 +689,19 @@ __device__ inline void tile_unit(double bound, double dvh, double &unit, bool &p
 // field once (plain read-modify-write; the tile owns its nodes), by x-rows:
 // TX lanes per row, rows (component, z, y).  A poisoned tile makes every node
 // NaN and raises the status flag.
+// acc == nullptr: a tile with nothing to add (only written when overwriting).
+// overwrite: every node of the tile is stored (zero where acc is), f is not
+// read; otherwise only nonzero sums are added.
 template <typename T, typename A_t, int TX, int TY, int TZ, int PX>
 __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0, int k0,
-                                  double unit, bool poison, T *f0, T *f1, T *f2,
+                                  double unit, bool poison, bool overwrite, T *f0, T *f1, T *f2,
                                   uint32_t *status) {
   constexpr bool kFixed = std::is_integral<A_t>::value;
   static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
   const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
   for (int row = threadIdx.x / TX; row < 3 * TZ * TY; row += kTileThreads / TX) {
-    const A_t a = acc[row * PX + lx];
-    if ((a == (A_t)0 && !poison) || i >= G.nx) continue;
+    const A_t a = acc ? acc[row * PX + lx] : (A_t)0;
+    if ((a == (A_t)0 && !poison && !overwrite) || i >= G.nx) continue;
     const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
     const int lz = rz / TY, ly = rz - lz * TY;
     const int j = j0 + ly, k = k0 + lz;
@@ -706,7 +709,11 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
     if (j >= nyc || k >= G.nz) continue;
     const size_t g = ((size_t)k * nyc + j) * G.nx + i;
     T *Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
-    Fp[g] += poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
+    const T v = poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
+    if (overwrite)
+      Fp[g] = v;
+    else
+      Fp[g] += v;
   }
   if (poison && threadIdx.x == 0) atomicOr(status, kFlagNonFinite);
 }
@@ -777,7 +784,12 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   // culled markers (the spheres have not moved since).
   const int cached = tc.mode == 2 ? tc.count[tile] : -1;   // uniform
   if (cached >= 0) {
-    if (cached == 0) return;
+    if (cached == 0) {
+      if (tc.overwrite)
+        tile_flush<T, A_t, TX, TY, TZ, PX>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
+                                           status);
+      return;
+    }
     const unsigned *reg = tc.items + (size_t)tile * tc.cap;
     const int ncand = tc.ncand[tile];
     for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
@@ -809,7 +821,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
       spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
     }
     __syncthreads();
-    tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, f0, f1, f2, status);
+    tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1,
+                                       f2, status);
     return;
   }
 
@@ -853,6 +866,9 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   const bool record = tc.mode == 1;
   if (nc == 0) {
     if (record && threadIdx.x == 0) tc.count[tile] = 0;
+    if (tc.overwrite)
+      tile_flush<T, A_t, TX, TY, TZ, PX>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
+                                         status);
     return;
   }
   if (nc > kTileCand) {
@@ -985,7 +1001,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     tc.ncand[tile] = nc;
   }
   __syncthreads();
-  tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, f0, f1, f2, status);
+  tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
+                                     status);
 }
 
 

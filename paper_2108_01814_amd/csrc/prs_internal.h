@@ -114,6 +114,10 @@ struct TileCache {
   unsigned *items;
   int *count;
   int *ncand;
+  // nonzero: f holds stale values and is overwritten, every node of the
+  // grid written once (zero where nothing is spread): clearing f fused into
+  // the pass
+  int overwrite = 0;
 };
 
 // ---- launchers (defined in the .hip files) ----

@@ -32,7 +32,7 @@ def orc():
     return oracle
 
 
-def run_both(P, orc, w, precision):
+def run_both(P, orc, w, precision, stale=0.0):
     import torch
 
     bed = W.make_bed(w)
@@ -40,10 +40,10 @@ def run_both(P, orc, w, precision):
     g = [a.to(device="cuda", dtype=dt).contiguous() for a in fields_for(w, bed)]
     x, u, om = (torch.as_tensor(a).cuda() for a in (bed.x, bed.u, bed.om))
     print(f"{w.name}: {w.n} spheres, D/h {w.d_over_h}, {w.n_markers} markers, "
-          f"precision {precision}", flush=True)
+          f"precision {precision}, f on entry {stale}", flush=True)
     with P.Context(prs_params(P, w, precision)) as ctx:
         H = P.History.zeros(w.n)
-        f = [torch.zeros_like(a) for a in g]
+        f = [torch.full_like(a, stale) for a in g]
         Fh, Th, st = ctx.step(g, f, x, u, om, H, zero_f=True)
         gpu = dict(Fh=Fh.cpu().numpy(), Th=Th.cpu().numpy(), x=x.cpu().numpy(),
                    f=[a.double().cpu().numpy() for a in f], st=st)
@@ -82,3 +82,32 @@ def test_brick_shapes(P, orc, d_over_h, nl, precision):
                 seed=23, bed_u_std=0.1)
     gpu, ref = run_both(P, orc, w, precision)
     check(gpu, ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_zero_f_overwrites_a_stale_field(P, orc, precision):
+    # zero_f: the first spreading pass stores every node of f instead of
+    # adding to it, so NaN left in f on entry must not survive anywhere
+    w = W.small("stale", 40, 10, (4.0, 6.0, 4.0), seed=25, bed_u_std=0.1)
+    gpu, ref = run_both(P, orc, w, precision, stale=float("nan"))
+    for c in range(3):
+        assert np.isfinite(gpu["f"][c]).all()
+    check(gpu, ref, TOL[precision])
+
+
+@pytest.mark.parametrize("kw", [dict(n_iter=0), dict(tol_mode=1, tol=2.0, max_iter=5)],
+                         ids=["no_iterations", "tolerance_met_at_once"])
+def test_zero_f_without_a_spreading_pass_clears_f(P, kw):
+    # no spreading pass runs: the field is cleared on its own
+    import torch
+
+    w = W.small("nospread", 20, 10, (4.0, 6.0, 4.0), seed=26)
+    bed = W.make_bed(w)
+    g = [a.to(device="cuda").contiguous() for a in fields_for(w, bed)]
+    x, u, om = (torch.as_tensor(a).cuda() for a in (bed.x, bed.u, bed.om))
+    with P.Context(prs_params(P, w, P.F64, **kw)) as ctx:
+        f = [torch.full_like(a, float("nan")) for a in g]
+        _, _, st = ctx.step(g, f, x, u, om, P.History.zeros(w.n), zero_f=True)
+    assert st["iterations"] == 0
+    for a in f:
+        assert bool((a == 0).all())

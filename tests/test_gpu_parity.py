@@ -303,7 +303,8 @@ def test_empty_step(P):
     w = TINY
     with P.Context(prs_params(P, w, P.F64)) as ctx:
         g = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in ctx.grid_shapes()]
-        f = [torch.zeros_like(a) for a in g]
+        f = [torch.full_like(a, float("nan")) for a in g]
         z = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
         Fh, Th, st = ctx.step(g, f, z, z.clone(), z.clone(), P.History.zeros(0), zero_f=True)
         assert Fh.shape == (0, 3) and st["iterations"] == 0
+        assert all(bool((a == 0).all()) for a in f)
