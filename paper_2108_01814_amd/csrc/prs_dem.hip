@@ -199,13 +199,27 @@ __global__ __launch_bounds__(256) void k_substep(
       }
     };
 
+    // Which candidates touch: a first pass over their positions, branch-free
+    // and unrolled so the gathers overlap, marks them in a bit mask; the
+    // contacts are then evaluated in candidate order.
+    static_assert(kCandCap <= 32, "candidate mask");
+    uint32_t touching = 0;
+#pragma unroll 4
     for (int a = 0; a < nk; ++a) {
       const int k = cand[a * N + j];
       const double dx = min_image(xs[k] - xp[0], G.Lx);
       const double dy = xs[N + k] - xp[1];
       const double dz = min_image(xs[2 * N + k] - xp[2], G.Lz);
       const double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (!(d2 < four_r2)) continue;
+      touching |= (d2 < four_r2 ? 1u : 0u) << a;
+    }
+    for (; touching; touching &= touching - 1u) {
+      const int a = __builtin_ctz(touching);
+      const int k = cand[a * N + j];
+      const double dx = min_image(xs[k] - xp[0], G.Lx);
+      const double dy = xs[N + k] - xp[1];
+      const double dz = min_image(xs[2 * N + k] - xp[2], G.Lz);
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
       const double dist = sqrt(d2);
       const double nrm[3] = {dx / dist, dy / dist, dz / dist};
       const double sw[3] = {wp[0] + ws[k], wp[1] + ws[N + k], wp[2] + ws[2 * N + k]};
