@@ -56,22 +56,27 @@ def touched_nodes(ctx, x, torch):
     return out
 
 
-def ib_bytes(w, n_touched, s):
-    """Algorithmic bytes of one interpolation and one spreading pass (the
-    same for every pass of the step).
+def ib_bytes(w, n_touched, s, iters):
+    """Algorithmic bytes of one interpolation and one spreading pass (for the
+    spreading, the mean over the step's passes).
 
     interpolation: read one field at every touched node (s per node and
     component: u-hat in the first pass, f in the later ones), write (first
     pass) or read (later passes) the markers' interpolated u-hat (3 s per
     marker), write the marker correction (3 s per marker), read the sphere
     state (9 doubles) and write the slip partials (2 doubles) per sphere.
-    spreading: read the correction (3 s per marker), read-modify-write f at
-    every touched node (2 s), read-modify-write the 12 force/torque
-    accumulators per sphere."""
+    spreading: read the correction (3 s per marker) and the sphere centres
+    (3 doubles), read-modify-write the 12 force/torque accumulators per
+    sphere; for f, the step's first pass (f cleared) stores every node of
+    the grid (s per node) and the later passes read-modify-write every
+    touched node (2 s), averaged over the step's `iters` passes."""
     M = w.n * w.n_markers
     NT = sum(n_touched)
+    nx, ny, nz = w.grid
+    nodes = nx * ny * nz * 2 + nx * (ny + 1) * nz
     interp = NT * s + M * 3 * s * 2 + w.n * (9 + 2) * 8
-    spread = M * 3 * s + NT * 2 * s + w.n * 3 * 8 + w.n * 12 * 8 * 2
+    f_bytes = (nodes * s + (iters - 1) * NT * 2 * s) / iters if iters > 0 else 0
+    spread = M * 3 * s + f_bytes + w.n * 3 * 8 + w.n * 12 * 8 * 2
     return interp, spread
 
 
@@ -373,7 +378,7 @@ def main(argv=None):
     iters = r32["stats"]["iterations"]
     t_ib = (tm["ms_interp"] + tm["ms_spread"]) / 1e3 / K
     t_dem = (tm["ms_search"] + tm["ms_substep"]) / 1e3 / K
-    b_interp, b_spread = ib_bytes(w, r32["touched"], 4)
+    b_interp, b_spread = ib_bytes(w, r32["touched"], 4, iters)
     avg_interp = tm["ms_interp"] / max(tm["n_interp"], 1)
     avg_spread = tm["ms_spread"] / max(tm["n_spread"], 1)
     kern = {"prs::k_interp<float, 0, false, 15>": (b_interp, avg_interp),
