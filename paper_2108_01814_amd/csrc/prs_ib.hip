@@ -111,6 +111,16 @@ enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2, kInterpFeat = 3, kInter
 #ifndef PRS_BRICK_ALL3_MAX_BYTES
 #define PRS_BRICK_ALL3_MAX_BYTES 0
 #endif
+// Chunks per lane held in registers by the software pipeline over the
+// components (0: no pipeline).  Single precision at D/h = 10 (3 chunks per
+// lane): 13.1 ms per pass with it, 13.9 without; 4 registers' worth of chunks
+// exceeds the 64 VGPRs of 8 waves per SIMD and is four times slower.
+#ifndef PRS_BRICK_PIPE_F32
+#define PRS_BRICK_PIPE_F32 3
+#endif
+#ifndef PRS_BRICK_PIPE_F64
+#define PRS_BRICK_PIPE_F64 0
+#endif
 template <typename T>
 struct BrickUnroll {
   static constexpr int value = sizeof(T) == 4 ? PRS_BRICK_UNROLL_F32 : PRS_BRICK_UNROLL_F64;
@@ -177,52 +187,107 @@ __global__ __launch_bounds__(1024) void k_interp(
   T U[3] = {(T)0, (T)0, (T)0};
   // ALL3: the bricks of the three components are staged together; otherwise
   // one component at a time.
+  // x-rows of the brick in chunks of VEC elements (16 bytes): one vector load
+  // per chunk, element-wise wrapped loads only for chunks that cross the
+  // periodic x boundary; rows padded to the pitch P in LDS
+  constexpr int VEC = 16 / sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  const int P = brick_pitch_c<T>(nb);
+  const int CPR = P / VEC;
+  const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
+  // chunk it of the brick of the components from c0 on (zero outside the
+  // fluid's rows)
+  auto load_chunk = [&](int c0, int it) {
+    vec_t v = (vec_t)(T)0;
+    const int row = it / CPR, ch = it - row * CPR;
+    const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
+    const int rr = row - cc * nb2;
+    const int bz = rr / nb, by = rr - bz * nb;
+    const int j = lo[c][1] + by;
+    if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
+      const int k = wrap_once(lo[c][2] + bz, G.nz);
+      const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
+      const int x0 = lo[c][0] + ch * VEC;
+      const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
+                            : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
+      if (x0 >= 0 && x0 + VEC <= G.nx) {
+        __builtin_memcpy(&v, Sp + x0, sizeof(vec_t));
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = Sp[wrap_once(x0 + e, G.nx)];
+      }
+    }
+    return v;
+  };
+  auto store_chunk = [&](int it, vec_t v) {
+    const int row = it / CPR, ch = it - row * CPR;
+    *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
+  };
+  // Software pipeline over the components when a lane holds at most kPipe
+  // chunks of one brick: the next component's chunks are loaded into
+  // registers while the current one's stencils run.
+  // (MDF passes only: the other modes hold more registers of their own)
+  constexpr int kPipeCfg =
+      MODE != kInterpMDF ? 0 : (sizeof(T) == 4 ? PRS_BRICK_PIPE_F32 : PRS_BRICK_PIPE_F64);
+  constexpr int kPipe = kPipeCfg > 0 ? kPipeCfg : 1;
+  const int per_comp = nb2 * CPR;
+  const bool pipe = !ALL3 && kPipeCfg > 0 && per_comp <= kPipe * (int)blockDim.x;
+  vec_t nxt[kPipe];
+  auto issue = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < kPipe; ++u) {
+      const int it = threadIdx.x + u * blockDim.x;
+      nxt[u] = it < per_comp ? load_chunk(c, it) : (vec_t)(T)0;
+    }
+  };
+  if (pipe) issue(0);
   for (int pass = 0; pass < (ALL3 ? 1 : 3); ++pass) {
     const int c0 = ALL3 ? 0 : pass, nc = ALL3 ? 3 : 1;
     __syncthreads();   // the previous pass's brick is no longer read
-    // x-rows of the brick in chunks of VEC elements (16 bytes): one vector
-    // load per chunk, element-wise wrapped loads only for chunks that cross
-    // the periodic x boundary; rows padded to the pitch P in LDS
-    constexpr int VEC = 16 / sizeof(T);
-    typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    const int P = brick_pitch_c<T>(nb);
-    const int CPR = P / VEC;
-    const int nitems = nc * nb2 * CPR;
-    const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
-    constexpr int kBrickUnroll = BrickUnroll<T>::value;
-    for (int it0 = threadIdx.x; it0 < nitems; it0 += blockDim.x * kBrickUnroll) {
-      vec_t v[kBrickUnroll];
+    if (pipe) {
 #pragma unroll
-      for (int u = 0; u < kBrickUnroll; ++u) {
-        const int it = it0 + u * blockDim.x;
-        v[u] = (vec_t)(T)0;
-        if (it < nitems) {
-          const int row = it / CPR, ch = it - row * CPR;
-          const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
-          const int rr = row - cc * nb2;
-          const int bz = rr / nb, by = rr - bz * nb;
-          const int j = lo[c][1] + by;
-          if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
-            const int k = wrap_once(lo[c][2] + bz, G.nz);
-            const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
-            const int x0 = lo[c][0] + ch * VEC;
-            const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
-                                  : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
-            if (x0 >= 0 && x0 + VEC <= G.nx) {
-              __builtin_memcpy(&v[u], Sp + x0, sizeof(vec_t));
-            } else {
+      for (int u = 0; u < kPipe; ++u) {
+        const int it = threadIdx.x + u * blockDim.x;
+        if (it < per_comp) store_chunk(it, nxt[u]);
+      }
+      if (pass < 2) issue(pass + 1);
+    } else {
+      const int nitems = nc * per_comp;
+      constexpr int kBrickUnroll = BrickUnroll<T>::value;
+      for (int it0 = threadIdx.x; it0 < nitems; it0 += blockDim.x * kBrickUnroll) {
+        vec_t v[kBrickUnroll];
 #pragma unroll
-              for (int e = 0; e < VEC; ++e) v[u][e] = Sp[wrap_once(x0 + e, G.nx)];
+        for (int u = 0; u < kBrickUnroll; ++u) {
+          const int it = it0 + u * blockDim.x;
+          v[u] = (vec_t)(T)0;
+          if (it < nitems) {
+            const int row = it / CPR, ch = it - row * CPR;
+            const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
+            const int rr = row - cc * nb2;
+            const int bz = rr / nb, by = rr - bz * nb;
+            const int j = lo[c][1] + by;
+            if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
+              const int k = wrap_once(lo[c][2] + bz, G.nz);
+              const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
+              const int x0 = lo[c][0] + ch * VEC;
+              const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
+                                    : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
+              if (x0 >= 0 && x0 + VEC <= G.nx) {
+                __builtin_memcpy(&v[u], Sp + x0, sizeof(vec_t));
+              } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[u][e] = Sp[wrap_once(x0 + e, G.nx)];
+              }
             }
           }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < kBrickUnroll; ++u) {
-        const int it = it0 + u * blockDim.x;
-        if (it < nitems) {
-          const int row = it / CPR, ch = it - row * CPR;
-          *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v[u];
+        for (int u = 0; u < kBrickUnroll; ++u) {
+          const int it = it0 + u * blockDim.x;
+          if (it < nitems) {
+            const int row = it / CPR, ch = it - row * CPR;
+            *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v[u];
+          }
         }
       }
     }
