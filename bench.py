@@ -254,12 +254,18 @@ KERNEL_SOURCES = ("prs_ib.hip", "prs_stencil.h", "prs_device.h", "prs_internal.h
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank space removed (a
+    change to a comment leaves the kernels, and their counters, as they were)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2108_01814_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2108_01814_amd", "csrc", name)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -252,6 +252,8 @@ __global__ __launch_bounds__(1024) void k_interp(
       }
       if (pass < 2) issue(pass + 1);
     } else {
+      // (load_chunk's loads written out in the loop: built on the lambda,
+      // this loop measured 9 % slower)
       const int nitems = nc * per_comp;
       constexpr int kBrickUnroll = BrickUnroll<T>::value;
       for (int it0 = threadIdx.x; it0 < nitems; it0 += blockDim.x * kBrickUnroll) {
