@@ -330,7 +330,46 @@ def cpu_baseline(W, w, bed, width=12.0):
                 sample=(f"{len(xs)} spheres ({len(xs) * w.n_markers} markers) with centres in a "
                         f"{width:g}D x {w.domain[1]:g}D x {width:g}D column of the same bed, "
                         f"one full step ({w.n_iter} forcing iterations, {ph['n_sub']} substeps), "
-                        f"FP64, {t:.1f}s"), rc=rc)
+                        f"FP64, {t:.1f}s"), rc=rc, host=host_description())
+
+
+def host_description():
+    """CPU model, logical CPUs and memory of the host that ran the oracle."""
+    model, mem_gb = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_gib": mem_gb}
+
+
+def copy_rate(torch, nbytes=2 << 30, reps=5):
+    """Measured device-to-device copy rate (bytes read + written per second)
+    of a plain torch copy of nbytes, best of reps: the achievable HBM rate
+    beside the 8 TB/s specification."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best / 1e3) / 1e9
 
 
 def main(argv=None):
@@ -392,6 +431,24 @@ def main(argv=None):
     dom = max(kern, key=lambda k: kern[k][1])
     bts, ms = kern[dom]
     achieved = bts / (ms / 1e3) / 1e9
+    copy_gbs = copy_rate(torch)
+    log(f"measured copy rate {copy_gbs:.0f} GB/s")
+    # the step's rates against the HBM roofline: the forcing (one
+    # interpolation and one spreading per iteration) and the substeps (per
+    # substep each sphere's state and cell data, about 160 B, and per directed
+    # contact its history slot read and written, 72 B)
+    t_iter = t_ib / iters if iters else None
+    b_iter = b_interp + b_spread
+    b_dem = W.PHYS["n_sub"] * w.n * 160 + (r32["contacts"] / K) * 72
+    rates = {
+        "forcing": {"alg_bytes_per_iteration": b_iter,
+                    "GBs": b_iter / t_iter / 1e9 if t_iter else None},
+        "substeps": {"alg_bytes_per_step": b_dem,
+                     "GBs": b_dem / t_dem / 1e9 if t_dem > 0 else None},
+    }
+    for v in rates.values():
+        v["frac"] = v["GBs"] / HBM_PEAK_GBS if v["GBs"] else None
+        v["frac_of_measured_copy"] = v["GBs"] / copy_gbs if v["GBs"] else None
     out = {
         "metric": METRIC,
         "value": w.n / t_step,
@@ -423,7 +480,10 @@ def main(argv=None):
                      "interp": {"alg_bytes": b_interp, "avg_ms": avg_interp,
                                 "GBs": b_interp / avg_interp / 1e6},
                      "spread": {"alg_bytes": b_spread, "avg_ms": avg_spread,
-                                "GBs": b_spread / avg_spread / 1e6}},
+                                "GBs": b_spread / avg_spread / 1e6},
+                     "measured_copy_GBs": copy_gbs,
+                     "frac_of_measured_copy": achieved / copy_gbs},
+        "rates_vs_roofline": rates,
     }
     if not args.no_fp64:
         K64 = max(1, min(K, 3))
