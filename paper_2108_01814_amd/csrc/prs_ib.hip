@@ -8,15 +8,20 @@
 // workgroup carries the same number of markers however dense the bed is
 // around it (the marker-based balancing of sec. 3.3 on one GPU).  The grid
 // brick around the sphere is staged in LDS (one velocity component at a time
-// unless all three fit in PRS_BRICK_ALL3_MAX_BYTES) with coalesced row loads;
-// the 27-point stencils then read LDS only.
+// unless all three fit in PRS_BRICK_ALL3_MAX_BYTES) with coalesced row loads,
+// the next component's loads in flight while the current one is computed;
+// the 27-point stencils then read LDS only.  Each pass loads one field: u-hat
+// in the step's first pass (whose result is recorded per marker), f in the
+// later ones (the recorded I[u-hat] added).
 //
 // Spreading: one workgroup per grid tile.  The tile gathers the spheres whose
-// markers can reach it from the cell list, accumulates their contributions to
-// the tile's own nodes with LDS atomics (double-precision accumulators), and
-// adds the tile to the force field
-// with plain coalesced read-modify-writes.  Every grid node belongs to exactly
-// one tile, so no global atomics are needed.
+// markers can reach it from the cell list (the step's first pass records
+// them, the later passes replay the record), accumulates their contributions
+// to the tile's own nodes with LDS atomics (32-bit fixed point for
+// single-precision fields, double precision otherwise), and adds the tile to
+// the force field with plain coalesced read-modify-writes (or stores every
+// node, when the pass also clears the field).  Every grid node belongs to
+// exactly one tile, so no global atomics are needed.
 #include <algorithm>
 #include <type_traits>
 
