@@ -420,6 +420,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     rc |= alloc(c, &S.xs[b], 3 * n);
     rc |= alloc(c, &S.us[b], 3 * n);
     rc |= alloc(c, &S.ws[b], 3 * n);
+    rc |= alloc(c, &S.pk[b], 12 * n);
     rc |= alloc(c, &S.h_cnt[b], n);
     rc |= alloc(c, &S.h_id[b], kSlots * n);
     rc |= alloc(c, &S.h_dt[b], 3 * kSlots * n);

@@ -147,10 +147,11 @@ __device__ inline void contact_law(const Mech &M, double R, double kn, double dn
 __global__ __launch_bounds__(256) void k_substep(
     Geom G, Mech M, int n, const int *__restrict__ perm, const int *__restrict__ ncand,
     const int *__restrict__ cand, const double *__restrict__ x0, const double *__restrict__ xs,
-    const double *__restrict__ us, const double *__restrict__ ws, const double *__restrict__ fh,
-    const double *__restrict__ th, const int *__restrict__ o_cnt, const int *__restrict__ o_id,
-    const double *__restrict__ o_dt, const double *__restrict__ o_uin, double *__restrict__ xd,
-    double *__restrict__ ud, double *__restrict__ wd, int *__restrict__ n_cnt,
+    const double *__restrict__ us, const double *__restrict__ ws, const double *__restrict__ pk,
+    const double *__restrict__ fh, const double *__restrict__ th, const int *__restrict__ o_cnt,
+    const int *__restrict__ o_id, const double *__restrict__ o_dt,
+    const double *__restrict__ o_uin, double *__restrict__ xd, double *__restrict__ ud,
+    double *__restrict__ wd, double *__restrict__ pd, int *__restrict__ n_cnt,
     int *__restrict__ n_id, double *__restrict__ n_dt, double *__restrict__ n_uin,
     uint32_t *status, unsigned long long *counters, int last) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,27 +207,28 @@ __global__ __launch_bounds__(256) void k_substep(
     uint32_t touching = 0;
 #pragma unroll 4
     for (int a = 0; a < nk; ++a) {
-      const int k = cand[a * N + j];
-      const double dx = min_image(xs[k] - xp[0], G.Lx);
-      const double dy = xs[N + k] - xp[1];
-      const double dz = min_image(xs[2 * N + k] - xp[2], G.Lz);
+      const double *q = pk + 12 * (size_t)cand[a * N + j];
+      const double dx = min_image(q[0] - xp[0], G.Lx);
+      const double dy = q[1] - xp[1];
+      const double dz = min_image(q[2] - xp[2], G.Lz);
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       touching |= (d2 < four_r2 ? 1u : 0u) << a;
     }
     for (; touching; touching &= touching - 1u) {
       const int a = __builtin_ctz(touching);
       const int k = cand[a * N + j];
-      const double dx = min_image(xs[k] - xp[0], G.Lx);
-      const double dy = xs[N + k] - xp[1];
-      const double dz = min_image(xs[2 * N + k] - xp[2], G.Lz);
+      const double *q = pk + 12 * (size_t)k;
+      const double dx = min_image(q[0] - xp[0], G.Lx);
+      const double dy = q[1] - xp[1];
+      const double dz = min_image(q[2] - xp[2], G.Lz);
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       const double dist = sqrt(d2);
       const double nrm[3] = {dx / dist, dy / dist, dz / dist};
-      const double sw[3] = {wp[0] + ws[k], wp[1] + ws[N + k], wp[2] + ws[2 * N + k]};
+      const double sw[3] = {wp[0] + q[8], wp[1] + q[9], wp[2] + q[10]};
       const double wxn[3] = {sw[1] * nrm[2] - sw[2] * nrm[1], sw[2] * nrm[0] - sw[0] * nrm[2],
                              sw[0] * nrm[1] - sw[1] * nrm[0]};
-      const double ucp[3] = {(up[0] - us[k]) + R * wxn[0], (up[1] - us[N + k]) + R * wxn[1],
-                             (up[2] - us[2 * N + k]) + R * wxn[2]};
+      const double ucp[3] = {(up[0] - q[4]) + R * wxn[0], (up[1] - q[5]) + R * wxn[1],
+                             (up[2] - q[6]) + R * wxn[2]};
       emit(perm[k], nrm, 2.0 * R - dist, ucp, false);
       ++my_pp;
     }
@@ -260,6 +262,9 @@ __global__ __launch_bounds__(256) void k_substep(
       xd[a * N + j] = xp[a];
       ud[a * N + j] = up[a];
       wd[a * N + j] = wp[a];
+      pd[12 * (size_t)j + a] = xp[a];
+      pd[12 * (size_t)j + 4 + a] = up[a];
+      pd[12 * (size_t)j + 8 + a] = wp[a];
     }
     if (!(xp[1] >= 0.0 && xp[1] <= G.Ly)) fl |= kFlagDomain;
     if (fl) atomicOr(status, fl);
@@ -281,10 +286,10 @@ hipError_t launch_substep(hipStream_t s, const Scratch &S, const Geom &G, const 
   if (n == 0) return hipSuccess;
   const int dst = 1 - src;
   hipLaunchKernelGGL(k_substep, dim3((n + 255) / 256), dim3(256), 0, s, G, M, n, S.perm, S.ncand,
-                     S.cand, S.x0, S.xs[src], S.us[src], S.ws[src], S.fh, S.th, S.h_cnt[src],
-                     S.h_id[src], S.h_dt[src], S.h_uin[src], S.xs[dst], S.us[dst], S.ws[dst],
-                     S.h_cnt[dst], S.h_id[dst], S.h_dt[dst], S.h_uin[dst], S.status, S.counters,
-                     last);
+                     S.cand, S.x0, S.xs[src], S.us[src], S.ws[src], S.pk[src], S.fh, S.th,
+                     S.h_cnt[src], S.h_id[src], S.h_dt[src], S.h_uin[src], S.xs[dst], S.us[dst],
+                     S.ws[dst], S.pk[dst], S.h_cnt[dst], S.h_id[dst], S.h_dt[dst], S.h_uin[dst],
+                     S.status, S.counters, last);
   return hipGetLastError();
 }
 

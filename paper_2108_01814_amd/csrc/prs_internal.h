@@ -65,6 +65,10 @@ struct Scratch {
   size_t scan_tmp_elems;
   // sorted sphere state, double-buffered SoA [3][n]
   double *xs[2], *us[2], *ws[2], *x0;
+  // the same state packed per sphere, [n][12] = x, 0, u, 0, omega, 0 (with
+  // one pad after each triple), double-buffered like xs: the substeps'
+  // gathers of a partner's state touch one or two cache lines, not nine
+  double *pk[2];
   double *fh, *th;            // [3][n] sorted
   double *ft_acc;             // [12][n]: (sum, compensation) x (Fx Fy Fz Tx Ty Tz)
   double *ft_part;            // [12][n]: the same for the latest interpolation pass

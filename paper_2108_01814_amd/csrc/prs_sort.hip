@@ -149,8 +149,8 @@ __global__ void k_gather_state(const int *__restrict__ perm, int n, Geom G,
                                const double *__restrict__ om, const int32_t *__restrict__ hp,
                                const double *__restrict__ hd, const double *__restrict__ hu,
                                const int8_t *__restrict__ hc, double *xs, double *us, double *ws,
-                               double *x0, int *inv_perm, int *h_cnt, int *h_id, double *h_dt,
-                               double *h_uin, uint32_t *status) {
+                               double *x0, double *pk, int *inv_perm, int *h_cnt, int *h_id,
+                               double *h_dt, double *h_uin, uint32_t *status) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int i = perm[j];
@@ -165,6 +165,9 @@ __global__ void k_gather_state(const int *__restrict__ perm, int n, Geom G,
     if (!isfinite(uv) || !isfinite(wv)) fl |= kFlagNonFinite;
     us[a * (size_t)n + j] = uv;
     ws[a * (size_t)n + j] = wv;
+    pk[12 * (size_t)j + a] = v;
+    pk[12 * (size_t)j + 4 + a] = uv;
+    pk[12 * (size_t)j + 8 + a] = wv;
   }
   int c = hc[i];
   if (c < 0 || c > kSlots) {
@@ -186,7 +189,8 @@ hipError_t launch_gather_state(hipStream_t s, const Scratch &S, const Geom &G, c
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_state, dim3((n + 255) / 256), dim3(256), 0, s, S.perm, n, G, x, u,
                      om, H->partner, H->delta_t, H->u_in, H->count, S.xs[0], S.us[0], S.ws[0],
-                     S.x0, S.inv_perm, S.h_cnt[0], S.h_id[0], S.h_dt[0], S.h_uin[0], S.status);
+                     S.x0, S.pk[0], S.inv_perm, S.h_cnt[0], S.h_id[0], S.h_dt[0], S.h_uin[0],
+                     S.status);
   return hipGetLastError();
 }
 
