@@ -27,10 +27,14 @@ __device__ inline unsigned order_key(int id) {
   return id >= 0 ? (unsigned)id : (id == PRS_WALL_BOTTOM ? 0x7ffffffeu : 0x7fffffffu);
 }
 
+// Sphere k's coordinate a is xs[a * cs + k * ss]: SoA [3][n] (cs = n, ss =
+// 1) or the packed state [n][12] (cs = 1, ss = 12), whose three coordinates
+// share a cache line.
 template <typename F>
 __device__ inline void for_each_near(const Cells &C, const Geom &G, const int *start,
-                                     const double *xs, int n, int j, double cut2, F fn) {
-  const double px = xs[j], py = xs[n + j], pz = xs[2 * n + j];
+                                     const double *xs, size_t cs, size_t ss, int j, double cut2,
+                                     F fn) {
+  const double px = xs[j * ss], py = xs[cs + j * ss], pz = xs[2 * cs + j * ss];
   const int cx = cell_coord(px, C.csx, C.ncx), cy = cell_coord(py, C.csy, C.ncy),
             cz = cell_coord(pz, C.csz, C.ncz);
   for (int dz = -1; dz <= 1; ++dz) {
@@ -44,9 +48,10 @@ __device__ inline void for_each_near(const Cells &C, const Geom &G, const int *s
         const int e = start[key + 1];
         for (int k = start[key]; k < e; ++k) {
           if (k == j) continue;
-          const double ddx = min_image(xs[k] - px, G.Lx);
-          const double ddy = xs[n + k] - py;
-          const double ddz = min_image(xs[2 * n + k] - pz, G.Lz);
+          const double *q = xs + k * ss;
+          const double ddx = min_image(q[0] - px, G.Lx);
+          const double ddy = q[cs] - py;
+          const double ddz = min_image(q[2 * cs] - pz, G.Lz);
           const double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
           if (d2 < cut2) fn(k);
         }
@@ -58,8 +63,9 @@ __device__ inline void for_each_near(const Cells &C, const Geom &G, const int *s
 // ---------------------------------------------------------------------------
 // collision search
 // ---------------------------------------------------------------------------
+// pk: the packed sphere state [n][12] (positions first).
 __global__ void k_candidates(Cells C, Geom G, const int *__restrict__ start,
-                             const int *__restrict__ perm, const double *__restrict__ xs, int n,
+                             const int *__restrict__ perm, const double *__restrict__ pk, int n,
                              double cut2, int *__restrict__ ncand, int *__restrict__ cand,
                              uint32_t *status) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,7 +74,7 @@ __global__ void k_candidates(Cells C, Geom G, const int *__restrict__ start,
   int key[kCandCap];
   int cnt = 0;
   bool over = false;
-  for_each_near(C, G, start, xs, n, j, cut2, [&](int k) {
+  for_each_near(C, G, start, pk, 1, 12, j, cut2, [&](int k) {
     if (cnt < kCandCap) {
       const int id = perm[k];
       int c = cnt - 1;
@@ -93,7 +99,7 @@ hipError_t launch_candidates(hipStream_t s, const Scratch &S, const Cells &C, co
                              int n, double cut) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_candidates, dim3((n + 127) / 128), dim3(128), 0, s, C, G, S.start, S.perm,
-                     S.xs[0], n, cut * cut, S.ncand, S.cand, S.status);
+                     S.pk[0], n, cut * cut, S.ncand, S.cand, S.status);
   return hipGetLastError();
 }
 
@@ -310,7 +316,7 @@ __global__ void k_contact_list(Cells C, Geom G, const int *__restrict__ start,
   const double R = G.R;
   int upper[kMaxPP];
   int nu = 0, all = 0;
-  for_each_near(C, G, start, xs, n, j, (2.0 * R) * (2.0 * R), [&](int k) {
+  for_each_near(C, G, start, xs, (size_t)n, 1, j, (2.0 * R) * (2.0 * R), [&](int k) {
     const int id = perm[k];
     ++all;
     if (id > i && nu < kMaxPP) upper[nu++] = id;
