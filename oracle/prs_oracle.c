@@ -456,8 +456,12 @@ static void cells_build(const or_params *P, int np, const double *x, or_cells *C
     C->ncx = (int)floor(Lx / D);
     C->ncy = (int)floor(Ly / D);
     C->ncz = (int)floor(Lz / D);
+    if (C->ncx < 1)
+        C->ncx = 1;
     if (C->ncy < 1)
         C->ncy = 1;
+    if (C->ncz < 1)
+        C->ncz = 1;
     C->cx = Lx / C->ncx;
     C->cy = Ly / C->ncy;
     C->cz = Lz / C->ncz;
@@ -480,6 +484,20 @@ static void cells_free(or_cells *C)
 {
     free(C->head);
     free(C->next);
+}
+
+/* Cells c - 1, c, c + 1 of a periodic axis of n cells, each listed once. */
+static int neighbour_cells(int c, int n, int out[3])
+{
+    int k = 0;
+    for (int d = -1; d <= 1; ++d) {
+        int v = (int)wrap_index(c + d, n), seen = 0;
+        for (int e = 0; e < k; ++e)
+            seen |= out[e] == v;
+        if (!seen)
+            out[k++] = v;
+    }
+    return k;
 }
 
 static int cmp_int(const void *a, const void *b)
@@ -508,14 +526,18 @@ static int find_partners(const or_params *P, int np, const double *x, const or_c
         int ci = cell_coord(x[3 * p], C->cx, C->ncx);
         int cj = cell_coord(x[3 * p + 1], C->cy, C->ncy);
         int ck = cell_coord(x[3 * p + 2], C->cz, C->ncz);
-        for (int dk = -1; dk <= 1; ++dk)
+        /* the distinct neighbour columns along each periodic axis: with fewer
+         * than three cells, ci - 1 and ci + 1 wrap onto the same cell, which
+         * must be visited once */
+        int xs[3], zs[3];
+        int nxs = neighbour_cells(ci, C->ncx, xs), nzs = neighbour_cells(ck, C->ncz, zs);
+        for (int a = 0; a < nzs; ++a)
             for (int dj = -1; dj <= 1; ++dj)
-                for (int di = -1; di <= 1; ++di) {
+                for (int b = 0; b < nxs; ++b) {
                     int j = cj + dj;
                     if (j < 0 || j >= C->ncy)
                         continue;
-                    int i = (int)wrap_index(ci + di, C->ncx);
-                    int k = (int)wrap_index(ck + dk, C->ncz);
+                    int i = xs[b], k = zs[a];
                     for (int q = C->head[((long)k * C->ncy + j) * C->ncx + i]; q >= 0; q = C->next[q])
                         if (q != p && in_contact(P, x, p, q)) {
                             if (nb == 64)

@@ -80,6 +80,41 @@ def test_contacts_match_numpy_definition(orc):
         assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("Lx,Lz", [(2.5, 2.5), (1.5, 4.0), (4.0, 2.2)])
+def test_cell_list_visits_each_cell_once_in_narrow_boxes(orc, Lx, Lz):
+    """Fewer than three collision cells along a periodic axis: the cells left
+    and right of a sphere's cell are the same cell (or the cell itself), and
+    each must be searched once.  Brute force, the cell list and the numpy
+    definition agree, and the substeps give bit-identical states."""
+    nx, nz = int(round(Lx / 0.1)), int(round(Lz / 0.1))
+    L = (Lx, 3.0, Lz)
+    p0 = params(orc, nx=nx, ny=30, nz=nz)
+    p1 = params(orc, nx=nx, ny=30, nz=nz, use_cells=1)
+    # a touching pair across the x seam and one in the interior
+    x = np.array([[0.05, 1.5, 0.3], [Lx - 0.4, 1.5, 0.3],
+                  [0.6, 0.8, Lz - 0.3], [0.6, 0.8 + 0.97, Lz - 0.3]])
+    for xx in (x, np.stack([RNG.uniform(0, Lx, 8), RNG.uniform(0.6, 2.4, 8),
+                            RNG.uniform(0, Lz, 8)], 1)):
+        ref = brute_pairs(xx, L, 0.5)
+        if (np.bincount(ref[ref[:, 1] >= 0].ravel(), minlength=len(xx)) > 12).any():
+            continue
+        rc0, a, _ = orc.contacts(p0, xx)
+        rc1, b, _ = orc.contacts(p1, xx)
+        assert rc0 == rc1 == 0
+        assert np.array_equal(a, ref) and np.array_equal(b, ref)
+    # forces: the doubled visit would double the pair force
+    states = []
+    for p in (p0, p1):
+        xs, us, oms = x.copy(), np.zeros_like(x), np.zeros_like(x)
+        H = orc.History(len(x))
+        zero = np.zeros_like(x)
+        rc, Fc, Tc = orc.dem(p, xs, us, oms, zero, zero, H)
+        assert rc == 0
+        states.append((xs, us, Fc))
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+
+
 def test_fcc_interior_spheres_touch_twelve(orc):
     """Dense packing: in an FCC lattice at spacing 2R(1 - 1e-6) every sphere
     touches exactly twelve others (the bound used by the contact history)."""
