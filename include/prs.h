@@ -242,15 +242,41 @@ int prs_mlp_get(prs_mlp *mlp, float *params, float *norm);
  * features, standardised inside, and Y comes back in target units; raw == 0:
  * X and Y in standardised units.  Asynchronous. */
 int prs_mlp_forward(prs_mlp *mlp, void *stream, const float *X, int32_t B, int raw, float *Y);
-/* Gradient of the loss (1/(3B)) sum (Y - T)^2 for standardised X [B][16] and
- * T [B][3] (device): grad (device, PRS_MLP_PARAMS FP32, nullable), loss
- * (HOST, nullable; synchronises when given). */
-int prs_mlp_grad(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
-                 float *grad, double *loss);
-/* One Adam step (gradient of the batch, bias-corrected update of the master
- * weights and of their BF16 copy) with learning rate lr; loss as above. */
+/* Backward pass: gradient of the loss (1/(3B)) sum (Y - T)^2 over the batch,
+ * for standardised inputs X [B][16] and targets T [B][3] (device FP32).  The
+ * forward pass is rerun inside (no activations are kept between calls); the
+ * back-propagated errors are rounded to BF16 where they feed the matrix
+ * cores, the bias gradients take them unrounded.  grad: device FP32
+ * [PRS_MLP_PARAMS] (nullable: the network keeps the latest gradient for
+ * prs_mlp_adam); loss: HOST (nullable; synchronises when given).  The batch
+ * sums are reduced in a fixed order, so the result does not depend on the
+ * launch. */
+int prs_mlp_backward(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
+                     float *grad, double *loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected with the
+ * network's step count) of the FP32 master weights with learning rate lr > 0
+ * from grad (device FP32 [PRS_MLP_PARAMS]; NULL: the latest backward's
+ * gradient); refreshes the BF16 copy.  Asynchronous. */
+int prs_mlp_adam(prs_mlp *mlp, void *stream, const float *grad, float lr);
+/* prs_mlp_backward followed by prs_mlp_adam on its gradient. */
 int prs_mlp_train_step(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
                        float lr, double *loss);
+/* Loss (1/(3B)) sum (Y - T)^2 of standardised X [B][16], T [B][3] (device)
+ * into *loss (HOST); forward pass only.  Synchronous. */
+int prs_mlp_loss(prs_mlp *mlp, void *stream, const float *X, const float *T, int32_t B,
+                 double *loss);
+/* Standardise count raw samples with the network's statistics:
+ * Xs = (X - mean) / std [count][16], Ts = (T - target mean) / target std
+ * [count][3] (device FP32; T and Ts nullable together).  Asynchronous. */
+int prs_mlp_standardize(prs_mlp *mlp, void *stream, const float *X, const float *T,
+                        int64_t count, float *Xs, float *Ts);
+/* Training-set statistics of count >= 2 raw samples X [count][16],
+ * T [count][3] (device FP32) into norm (HOST, PRS_MLP_NORM values, the
+ * layout prs_mlp_create takes): means and sample standard deviations
+ * (denominator count - 1) in FP64, reduced in a fixed order; the four padding
+ * features get mean 0 and std 1, a constant column std 1.  Allocates a small
+ * scratch buffer.  Synchronous.  PRS_EINVAL for count < 2 or NULL arrays. */
+int prs_mlp_fit_norm(void *stream, const float *X, const float *T, int64_t count, float *norm);
 
 /* Attach a network to a context (NULL detaches).  A step on a context with a
  * network starts the multi-direct forcing from the network's prediction: one

@@ -28,7 +28,8 @@ _NAMES = {1: "EINVAL", 2: "ECAPACITY", 3: "EDOMAIN", 4: "ENONFINITE", 5: "EHIP",
 EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_interpolate",
            "prs_spread", "prs_contacts", "prs_step_particles", "prs_timing_enable",
            "prs_timing_read", "prs_mlp_create", "prs_mlp_destroy", "prs_mlp_last_error",
-           "prs_mlp_get", "prs_mlp_forward", "prs_mlp_grad", "prs_mlp_train_step",
+           "prs_mlp_get", "prs_mlp_forward", "prs_mlp_backward", "prs_mlp_adam",
+           "prs_mlp_train_step", "prs_mlp_loss", "prs_mlp_standardize", "prs_mlp_fit_norm",
            "prs_set_learned", "prs_forcing_samples")
 MLP_PARAMS = 6288
 MLP_NORM = 38
@@ -124,7 +125,11 @@ def lib():
         L.prs_mlp_last_error.restype = C.c_char_p
         L.prs_mlp_get.argtypes = [vp, vp, vp]
         L.prs_mlp_forward.argtypes = [vp, vp, vp, C.c_int32, C.c_int, vp]
-        L.prs_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+        L.prs_mlp_backward.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+        L.prs_mlp_adam.argtypes = [vp, vp, vp, C.c_float]
+        L.prs_mlp_loss.argtypes = [vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_double)]
+        L.prs_mlp_standardize.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp]
+        L.prs_mlp_fit_norm.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.prs_mlp_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float,
                                          C.POINTER(C.c_double)]
         _lib = L
@@ -442,6 +447,7 @@ class Mlp:
         return Y
 
     def grad(self, X, T):
+        """Gradient of the loss and the loss (prs_mlp_backward)."""
         import torch
 
         B = X.shape[0]
@@ -449,9 +455,15 @@ class Mlp:
         self._chk(T, (B, 3), "T")
         g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
         loss = C.c_double()
-        self._err(lib().prs_mlp_grad(self._h, _stream_ptr(), _ptr(X), _ptr(T), B, _ptr(g),
-                                     C.byref(loss)))
+        self._err(lib().prs_mlp_backward(self._h, _stream_ptr(), _ptr(X), _ptr(T), B, _ptr(g),
+                                         C.byref(loss)))
         return g, loss.value
+
+    def adam(self, grad=None, lr: float = 1e-3):
+        """One Adam step from grad (device FP32) or the latest backward's."""
+        if grad is not None:
+            self._chk(grad, (MLP_PARAMS,), "grad")
+        self._err(lib().prs_mlp_adam(self._h, _stream_ptr(), _ptr(grad), float(lr)))
 
     def train_step(self, X, T, lr: float = 1e-3, want_loss: bool = True):
         B = X.shape[0]
@@ -461,3 +473,44 @@ class Mlp:
         self._err(lib().prs_mlp_train_step(self._h, _stream_ptr(), _ptr(X), _ptr(T), B,
                                            float(lr), C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+    def loss(self, X, T) -> float:
+        """Mean square error of the standardised prediction (forward only)."""
+        B = X.shape[0]
+        self._chk(X, (B, 16), "X")
+        self._chk(T, (B, 3), "T")
+        loss = C.c_double()
+        self._err(lib().prs_mlp_loss(self._h, _stream_ptr(), _ptr(X), _ptr(T), B,
+                                     C.byref(loss)))
+        return loss.value
+
+    def standardize(self, X, T=None):
+        """(X - mean) / std and (T - target mean) / target std with the
+        network's statistics, as new device tensors."""
+        import torch
+
+        m = X.shape[0]
+        self._chk(X, (m, 16), "X")
+        if T is not None:
+            self._chk(T, (m, 3), "T")
+        Xs = torch.empty_like(X)
+        Ts = torch.empty_like(T) if T is not None else None
+        self._err(lib().prs_mlp_standardize(self._h, _stream_ptr(), _ptr(X), _ptr(T), m,
+                                            _ptr(Xs), _ptr(Ts)))
+        return Xs, Ts
+
+    @staticmethod
+    def fit_norm(X, T):
+        """Normalisation vector (feature mean/std, target mean/std) of raw
+        samples X [m, 16], T [m, 3] on the device (prs_mlp_fit_norm)."""
+        import numpy as np
+
+        m = X.shape[0]
+        Mlp._chk(X, (m, 16), "X")
+        Mlp._chk(T, (m, 3), "T")
+        nv = np.zeros(MLP_NORM, np.float32)
+        rc = lib().prs_mlp_fit_norm(_stream_ptr(), _ptr(X), _ptr(T), m,
+                                    C.c_void_p(nv.ctypes.data))
+        if rc != PRS_OK:
+            raise PrsError(rc, "prs_mlp_fit_norm failed")
+        return nv

@@ -143,19 +143,43 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_train(
   if ((threadIdx.x & 63) == 0) loss_part[gwave] = lsum;
 }
 
-// grad[i] = sum over waves of partial[w][i] (FP64 sum in wave order).
-__global__ void k_mlp_reduce(const float *__restrict__ partial, int nwaves, float *grad,
-                             const float *__restrict__ loss_part, double *loss, int B) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kMlpParams) {
-    double a = 0.0;
-    for (int w = 0; w < nwaves; ++w) a += (double)partial[(size_t)w * kMlpParams + i];
-    grad[i] = (float)a;
+// grad[i] = sum over waves w of partial[w][i], in a fixed order that does
+// not depend on the launch: block b takes parameters 64 b .. 64 b + 63;
+// wave v of the block sums (FP64) the partials of waves v, v + 16, v + 32,
+// ... in that order, then lane i of wave 0 adds the 16 wave sums in wave
+// order.  Reads are coalesced rows of 64 parameters.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_mlp_reduce(const float *__restrict__ partial,
+                                                              int nwaves, float *grad) {
+  __shared__ double s[kRedWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double a = 0.0;
+  if (i < kMlpParams)
+    for (int w = wv; w < nwaves; w += kRedWaves) a += (double)partial[(size_t)w * kMlpParams + i];
+  s[wv][lane] = a;
+  __syncthreads();
+  if (wv == 0 && i < kMlpParams) {
+    double t = s[0][lane];
+    for (int v = 1; v < kRedWaves; ++v) t += s[v][lane];
+    grad[i] = (float)t;
   }
-  if (i == 0) {
-    double a = 0.0;
-    for (int w = 0; w < nwaves; ++w) a += (double)loss_part[w];
-    *loss = a / (3.0 * (double)B);
+}
+
+// *out = scale * sum of part[0 .. n-1]: thread t sums part[t], part[t + 1024],
+// ... in that order, then thread 0 adds the 1024 thread sums in order.
+__global__ __launch_bounds__(1024) void k_sum_ordered(const float *__restrict__ part, int n,
+                                                      double scale, double *out) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  for (int w = threadIdx.x; w < n; w += blockDim.x) a += (double)part[w];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)blockDim.x; ++k) t += s[k];
+    *out = scale * t;
   }
 }
 
@@ -217,6 +241,108 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const unsigned short *__res
   }
 }
 
+// Loss of standardised inputs X [B][16] against standardised targets T
+// [B][3]: block b writes the sum of (Y - T)^2 over its tiles (wave sums in
+// wave order) to part[b].
+__global__ __launch_bounds__(256) void k_mlp_loss(const unsigned short *__restrict__ wbf,
+                                                  const float *__restrict__ master,
+                                                  const float *__restrict__ X,
+                                                  const float *__restrict__ T, int B,
+                                                  float *__restrict__ part) {
+  __shared__ MlpLds L;
+  __shared__ float wsum[4];
+  mlp_stage(L, wbf, master, false);
+  __syncthreads();
+  const int r = threadIdx.x & 15, q = (threadIdx.x >> 4) & 3, wave = threadIdx.x >> 6;
+  const int ntiles = (B + 15) / 16;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  float e2 = 0.f;
+  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+    const int m = tile * 16 + r;
+    const bool valid = m < B;
+    f32x4 xv = zero;
+    if (valid) xv = *reinterpret_cast<const f32x4 *>(X + (size_t)m * kMlpIn + 4 * q);
+    MlpFwd s;
+    mlp_forward_tile(L, pack4(xv), s);
+    if (valid && q == 0)
+      for (int i = 0; i < kMlpUsed; ++i) {
+        const float e = s.y[i] - T[(size_t)m * kMlpUsed + i];
+        e2 += e * e;
+      }
+  }
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
+  if ((threadIdx.x & 63) == 0) wsum[wave] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
+// Training-set statistics: column c < 16 of X [m][16], column 16 + c of T
+// [m][3].  pass 0: per-block sums of the columns; pass 1: per-block sums of
+// the squared deviations from mean[].  Thread t of block b takes rows
+// b * 256 + t, then + gridDim * 256, ... (FP64, fixed order), the block adds
+// its threads in a fixed tree; out[b][19].
+constexpr int kStatCols = kMlpIn + kMlpUsed;
+constexpr int kStatBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_col_sums(const float *__restrict__ X,
+                                                  const float *__restrict__ T, long long m,
+                                                  const double *__restrict__ mean, int pass,
+                                                  double *__restrict__ out) {
+  __shared__ double s[256];
+  double a[kStatCols];
+  for (int c = 0; c < kStatCols; ++c) a[c] = 0.0;
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < m;
+       row += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < kStatCols; ++c) {
+      double v = c < kMlpIn ? (double)X[row * kMlpIn + c] : (double)T[row * kMlpUsed + c - kMlpIn];
+      if (pass) {
+        v -= mean[c];
+        v *= v;
+      }
+      a[c] += v;
+    }
+  }
+  for (int c = 0; c < kStatCols; ++c) {
+    s[threadIdx.x] = a[c];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x * kStatCols + c] = s[0];
+    __syncthreads();
+  }
+}
+
+// dst[c] = sum over blocks of part[b][c] in block order, times scale (or,
+// with root = 1, the square root of that times scale).
+__global__ void k_col_final(const double *__restrict__ part, int nblocks, double scale, int root,
+                            double *dst) {
+  const int c = threadIdx.x;
+  if (c >= kStatCols) return;
+  double t = 0.0;
+  for (int b = 0; b < nblocks; ++b) t += part[b * kStatCols + c];
+  t *= scale;
+  dst[c] = root ? sqrt(t) : t;
+}
+
+// Xs = (X - mean) / std, Ts = (T - tmean) / tstd with the network's
+// statistics, each value formed in FP64 and rounded to FP32.
+__global__ void k_standardize(const float *__restrict__ norm, const float *__restrict__ X,
+                              const float *__restrict__ T, long long m, float *__restrict__ Xs,
+                              float *__restrict__ Ts) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m * kMlpIn) {
+    const int c = (int)(e % kMlpIn);
+    Xs[e] = (float)(((double)X[e] - (double)norm[c]) / (double)norm[kMlpIn + c]);
+  }
+  if (T && e < m * kMlpUsed) {
+    const int c = (int)(e % kMlpUsed);
+    Ts[e] = (float)(((double)T[e] - (double)norm[2 * kMlpIn + c]) /
+                    (double)norm[2 * kMlpIn + kMlpUsed + c]);
+  }
+}
+
 }  // namespace prs
 
 using namespace prs;
@@ -264,9 +390,63 @@ int mlp_grad(prs_mlp *mlp, hipStream_t s, const float *X, const float *T, int B)
   hipLaunchKernelGGL(k_mlp_train, dim3(nwg), dim3(64 * kMlpWaves), 0, s, mlp->wbf, mlp->master, X,
                      T, B, tpw, mlp->partial, mlp->loss_part);
   MLP_TRY(mlp, hipGetLastError());
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, mlp->partial,
-                     nwg * kMlpWaves, mlp->grad, mlp->loss_part, mlp->loss, B);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 63) / 64), dim3(64 * kRedWaves), 0, s,
+                     mlp->partial, nwg * kMlpWaves, mlp->grad);
+  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(1024), 0, s, mlp->loss_part, nwg * kMlpWaves,
+                     1.0 / (3.0 * (double)B), mlp->loss);
   MLP_TRY(mlp, hipGetLastError());
+  return PRS_OK;
+}
+
+// One bias-corrected Adam step on the master weights from g (device).
+int mlp_adam(prs_mlp *m, hipStream_t s, const float *g, float lr) {
+  m->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, m->master, m->m,
+                     m->v, g, m->wbf, lr, b1, b2, 1e-8f, c1, c2);
+  MLP_TRY(m, hipGetLastError());
+  return PRS_OK;
+}
+
+int copy_loss(prs_mlp *m, hipStream_t s, double *loss) {
+  if (!loss) return PRS_OK;
+  MLP_TRY(m, hipMemcpyAsync(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  MLP_TRY(m, hipStreamSynchronize(s));
+  return PRS_OK;
+}
+
+// Training-set statistics into norm (host) with the caller's scratch: part
+// [kStatBlocks][kStatCols] and stat [2][kStatCols] doubles on the device.
+// Every entry of the scratch is written before it is read.
+int fit_norm_with(hipStream_t s, const float *X, const float *T, int64_t count, double *part,
+                  double *stat, float *norm) {
+  double host[2 * kStatCols];
+  hipLaunchKernelGGL(k_col_sums, dim3(kStatBlocks), dim3(256), 0, s, X, T, (long long)count,
+                     nullptr, 0, part);
+  hipLaunchKernelGGL(k_col_final, dim3(1), dim3(64), 0, s, part, kStatBlocks,
+                     1.0 / (double)count, 0, stat);
+  hipLaunchKernelGGL(k_col_sums, dim3(kStatBlocks), dim3(256), 0, s, X, T, (long long)count,
+                     stat, 1, part);
+  // sample standard deviation (n - 1 in the denominator)
+  hipLaunchKernelGGL(k_col_final, dim3(1), dim3(64), 0, s, part, kStatBlocks,
+                     1.0 / (double)(count - 1), 1, stat + kStatCols);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(host, stat, sizeof host, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return PRS_EHIP;
+  // the padding features stay unscaled; a constant column keeps std 1
+  for (int c = 0; c < kMlpIn; ++c) {
+    const bool pad = c >= kMlpFeat;
+    norm[c] = pad ? 0.f : (float)host[c];
+    const double sd = host[kStatCols + c];
+    norm[kMlpIn + c] = (pad || !(sd > 0)) ? 1.f : (float)sd;
+  }
+  for (int c = 0; c < kMlpUsed; ++c) {
+    norm[2 * kMlpIn + c] = (float)host[kMlpIn + c];
+    const double sd = host[kStatCols + kMlpIn + c];
+    norm[2 * kMlpIn + kMlpUsed + c] = sd > 0 ? (float)sd : 1.f;
+  }
   return PRS_OK;
 }
 
@@ -342,19 +522,21 @@ int prs_mlp_forward(prs_mlp *m, void *stream, const float *X, int32_t B, int raw
   return PRS_OK;
 }
 
-int prs_mlp_grad(prs_mlp *m, void *stream, const float *X, const float *T, int32_t B, float *grad,
-                 double *loss) {
+int prs_mlp_backward(prs_mlp *m, void *stream, const float *X, const float *T, int32_t B,
+                     float *grad, double *loss) {
   if (!m) return PRS_EINVAL;
-  if (B <= 0 || !X || !T) return mfail(m, PRS_EINVAL, "grad: bad arguments");
+  if (B <= 0 || !X || !T) return mfail(m, PRS_EINVAL, "backward: bad arguments");
   hipStream_t s = st(stream);
   if (int rc = mlp_grad(m, s, X, T, B)) return rc;
   if (grad)
     MLP_TRY(m, hipMemcpyAsync(grad, m->grad, kMlpParams * 4, hipMemcpyDeviceToDevice, s));
-  if (loss) {
-    MLP_TRY(m, hipMemcpyAsync(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
-    MLP_TRY(m, hipStreamSynchronize(s));
-  }
-  return PRS_OK;
+  return copy_loss(m, s, loss);
+}
+
+int prs_mlp_adam(prs_mlp *m, void *stream, const float *grad, float lr) {
+  if (!m) return PRS_EINVAL;
+  if (!(lr > 0)) return mfail(m, PRS_EINVAL, "adam: learning rate must be positive");
+  return mlp_adam(m, st(stream), grad ? grad : m->grad, lr);
 }
 
 int prs_mlp_train_step(prs_mlp *m, void *stream, const float *X, const float *T, int32_t B,
@@ -363,17 +545,51 @@ int prs_mlp_train_step(prs_mlp *m, void *stream, const float *X, const float *T,
   if (B <= 0 || !X || !T || !(lr > 0)) return mfail(m, PRS_EINVAL, "train: bad arguments");
   hipStream_t s = st(stream);
   if (int rc = mlp_grad(m, s, X, T, B)) return rc;
-  m->t += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
-  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, m->master, m->m,
-                     m->v, m->grad, m->wbf, lr, b1, b2, 1e-8f, c1, c2);
+  if (int rc = mlp_adam(m, s, m->grad, lr)) return rc;
+  return copy_loss(m, s, loss);
+}
+
+int prs_mlp_loss(prs_mlp *m, void *stream, const float *X, const float *T, int32_t B,
+                 double *loss) {
+  if (!m) return PRS_EINVAL;
+  if (B <= 0 || !X || !T || !loss) return mfail(m, PRS_EINVAL, "loss: bad arguments");
+  hipStream_t s = st(stream);
+  const int tiles = (B + 15) / 16;
+  int grid = (tiles + 3) / 4;
+  if (grid > m->max_waves) grid = m->max_waves;
+  hipLaunchKernelGGL(k_mlp_loss, dim3(grid), dim3(256), 0, s, m->wbf, m->master, X, T, B,
+                     m->loss_part);
+  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(1024), 0, s, m->loss_part, grid,
+                     1.0 / (3.0 * (double)B), m->loss);
   MLP_TRY(m, hipGetLastError());
-  if (loss) {
-    MLP_TRY(m, hipMemcpyAsync(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, s));
-    MLP_TRY(m, hipStreamSynchronize(s));
-  }
+  return copy_loss(m, s, loss);
+}
+
+int prs_mlp_standardize(prs_mlp *m, void *stream, const float *X, const float *T, int64_t count,
+                        float *Xs, float *Ts) {
+  if (!m) return PRS_EINVAL;
+  if (count < 0 || (count > 0 && (!X || !Xs || (T && !Ts))))
+    return mfail(m, PRS_EINVAL, "standardize: bad arguments");
+  if (count == 0) return PRS_OK;
+  const long long n = (long long)count * kMlpIn;
+  hipLaunchKernelGGL(k_standardize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st(stream),
+                     m->norm, X, T, (long long)count, Xs, Ts);
+  MLP_TRY(m, hipGetLastError());
   return PRS_OK;
+}
+
+int prs_mlp_fit_norm(void *stream, const float *X, const float *T, int64_t count, float *norm) {
+  if (count < 2 || !X || !T || !norm) return PRS_EINVAL;
+  double *part = nullptr, *stat = nullptr;
+  if (hipMalloc(&part, sizeof(double) * kStatBlocks * kStatCols) != hipSuccess) return PRS_EHIP;
+  if (hipMalloc(&stat, sizeof(double) * 2 * kStatCols) != hipSuccess) {
+    (void)hipFree(part);
+    return PRS_EHIP;
+  }
+  const int rc = fit_norm_with(st(stream), X, T, count, part, stat, norm);
+  (void)hipFree(part);
+  (void)hipFree(stat);
+  return rc;
 }
 
 }  // extern "C"

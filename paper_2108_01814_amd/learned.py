@@ -3,12 +3,12 @@
 Samples come from the plain multi-direct forcing itself: for a sphere bed and
 a fluid field, prs_forcing_samples returns every marker's features and the
 forcing the plain iteration reaches after n_iter passes (times alpha dt).  A
-seeded random subset of the markers is kept, features and targets are
-standardised with the training set's mean and standard deviation, and the
-network is fitted by Adam on the device (prs_mlp_train_step: the library's
-own forward and backward kernels).  Sampling and batching here are index
-bookkeeping on device tensors; all arithmetic of the network runs in the
-library."""
+seeded random subset of the markers is kept; the library computes the
+training set's mean and standard deviation (prs_mlp_fit_norm), standardises
+the samples (prs_mlp_standardize) and fits the network by Adam on the device
+(prs_mlp_train_step: its own forward and backward kernels).  The random
+batch indices are drawn here and the batches gathered by index (data
+movement); all arithmetic on the samples runs in the library."""
 from __future__ import annotations
 
 from dataclasses import dataclass
@@ -87,27 +87,9 @@ def collect(w: W.Workload, snapshots: Sequence[tuple], n_iter: int = 30, keep: f
 
 
 def fit_norm(S: Samples) -> np.ndarray:
-    """Normalisation vector: feature mean/std (padding: 0/1), target mean/std."""
-    X = S.X.double()
-    T = S.T.double()
-    mean = X.mean(0).cpu().numpy()
-    std = X.std(0).cpu().numpy()
-    mean[N_FEAT:] = 0.0
-    std[N_FEAT:] = 1.0
-    std[std <= 0] = 1.0
-    tm = T.mean(0).cpu().numpy()
-    ts = T.std(0).cpu().numpy()
-    ts[ts <= 0] = 1.0
-    return np.concatenate([mean, std, tm, ts]).astype(np.float32)
-
-
-def standardise(S: Samples, norm: np.ndarray):
-    import torch
-
-    n = torch.as_tensor(norm, device=S.X.device)
-    Xs = ((S.X - n[:16]) / n[16:32]).contiguous()
-    Ts = ((S.T - n[32:35]) / n[35:38]).contiguous()
-    return Xs, Ts
+    """Normalisation vector: feature mean/std (padding: 0/1), target mean/std,
+    computed by the library (prs_mlp_fit_norm)."""
+    return Mlp.fit_norm(S.X, S.T)
 
 
 def train(S: Samples, iters: int = 2000, batch: int = 65536, lr: float = 1e-3, seed: int = 0,
@@ -116,8 +98,8 @@ def train(S: Samples, iters: int = 2000, batch: int = 65536, lr: float = 1e-3, s
     import torch
 
     norm = fit_norm(S)
-    Xs, Ts = standardise(S, norm)
     net = Mlp(Mlp.init_params(seed), norm)
+    Xs, Ts = net.standardize(S.X, S.T)
     gen = torch.Generator(device=Xs.device)
     gen.manual_seed(seed + 1)
     m = Xs.shape[0]
@@ -137,11 +119,12 @@ def train(S: Samples, iters: int = 2000, batch: int = 65536, lr: float = 1e-3, s
 
 
 def validation_loss(net: Mlp, S: Samples, norm: np.ndarray, batch: int = 1 << 20) -> float:
-    """Mean square error of the standardised prediction on held-out samples."""
-    Xs, Ts = standardise(S, norm)
+    """Mean square error of the standardised prediction on held-out samples
+    (the library's standardisation and loss; norm must be the network's)."""
     tot, cnt = 0.0, 0
-    for a in range(0, Xs.shape[0], batch):
-        Y = net.forward(Xs[a:a + batch].contiguous(), raw=False)
-        tot += float(((Y - Ts[a:a + batch]) ** 2).sum())
-        cnt += Y.numel()
+    for a in range(0, S.X.shape[0], batch):
+        Xs, Ts = net.standardize(S.X[a:a + batch].contiguous(), S.T[a:a + batch].contiguous())
+        B = Xs.shape[0]
+        tot += net.loss(Xs, Ts) * B
+        cnt += B
     return tot / max(cnt, 1)

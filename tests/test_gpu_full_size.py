@@ -8,8 +8,11 @@ column plus a 1D margin) and the spheres at least 4D inside the column are
 compared: what a sphere's step depends on reaches a few diameters (three
 forcing passes of stencil width, contacts a few neighbours deep with
 geometrically decaying weight), so the column's missing surroundings do not
-reach them.  Contact detection is compared bit-exactly on the whole bed (the
-oracle's cell-list detector is linear in the sphere count)."""
+reach them.  The force field f is compared on the node columns at least
+F_CORE_MARGIN inside the column (they receive spreading only from spheres at
+least F_CORE_MARGIN - D inside).  Contact detection is compared bit-exactly
+on the whole bed (the oracle's cell-list detector is linear in the sphere
+count)."""
 import math
 
 import numpy as np
@@ -20,7 +23,18 @@ from paper_2108_01814_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-WIDTH, CORE_MARGIN, FIELD_MARGIN = 12.0, 4.0, 1.0
+WIDTH, CORE_MARGIN, FIELD_MARGIN, F_CORE_MARGIN = 12.0, 4.0, 1.0, 5.0
+
+
+def column(w):
+    """Corner of the compared column and the node window of its field."""
+    h = w.h
+    x0 = 0.5 * (w.domain[0] - WIDTH)
+    z0 = 0.5 * (w.domain[2] - WIDTH)
+    wi0 = int(math.floor((x0 - FIELD_MARGIN) / h))
+    wk0 = int(math.floor((z0 - FIELD_MARGIN) / h))
+    wnx = wnz = int(math.ceil((WIDTH + 2 * FIELD_MARGIN) / h))
+    return x0, z0, wi0, wnx, wk0, wnz
 
 
 @pytest.fixture(scope="module")
@@ -64,6 +78,7 @@ def c3(P):
         out = dict(Fh=Fh.cpu().numpy(), Th=Th.cpu().numpy(), x=x.cpu().numpy(),
                    u=u.cpu().numpy(), om=om.cpu().numpy(), partner=H.partner.cpu().numpy(),
                    count=H.count.cpu().numpy().astype(np.int32), st=st)
+        out["f_window"] = window_field(w, f, *column(w)[2:])
         del f
     return w, bed, g, out
 
@@ -86,15 +101,11 @@ def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
     ph = W.PHYS
     nx, ny, nz = w.grid
     h = w.h
-    x0 = 0.5 * (w.domain[0] - WIDTH)
-    z0 = 0.5 * (w.domain[2] - WIDTH)
+    x0, z0, wi0, wnx, wk0, wnz = column(w)
     sel = ((bed.x[:, 0] >= x0) & (bed.x[:, 0] < x0 + WIDTH) &
            (bed.x[:, 2] >= z0) & (bed.x[:, 2] < z0 + WIDTH))
     win = np.nonzero(sel)[0]
     xs, us, oms = (np.ascontiguousarray(a[sel]) for a in (bed.x, bed.u, bed.om))
-    wi0 = int(math.floor((x0 - FIELD_MARGIN) / h))
-    wk0 = int(math.floor((z0 - FIELD_MARGIN) / h))
-    wnx = wnz = int(math.ceil((WIDTH + 2 * FIELD_MARGIN) / h))
     uh = window_field(w, g, wi0, wnx, wk0, wnz)
     po = orc.make_params(nx=nx, ny=ny, nz=nz, h=h, wi0=wi0 % nx, wnx=wnx, wk0=wk0 % nz, wnz=wnz,
                          R=0.5 * ph["D"], nl=w.n_markers, g=ph["g"], rho_p=ph["rho_p"],
@@ -120,6 +131,18 @@ def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
     assert np.abs(gpu["x"][gi] - xs[core]).max() < tol
     assert rel_err(gpu["u"][gi], us[core]) < tol
     assert rel_err(gpu["om"][gi], oms[core]) < tol
+    # the force field on the core node columns (every component, every row)
+    i0 = int(math.ceil((x0 + F_CORE_MARGIN) / h)) - wi0
+    i1 = int(math.floor((x0 + WIDTH - F_CORE_MARGIN) / h)) - wi0
+    k0 = int(math.ceil((z0 + F_CORE_MARGIN) / h)) - wk0
+    k1 = int(math.floor((z0 + WIDTH - F_CORE_MARGIN) / h)) - wk0
+    assert i1 - i0 >= 15 and k1 - k0 >= 15
+    for c in range(3):
+        a = gpu["f_window"][c][k0:k1, :, i0:i1]
+        b = f[c][k0:k1, :, i0:i1]
+        assert np.abs(b).max() > 0
+        print(f"C3 column core f[{c}]: error {rel_err(a, b):.2e}", flush=True)
+        assert rel_err(a, b) < tol
     # contact histories: the same partners (window indices mapped to the bed's)
     assert np.array_equal(gpu["count"][gi], H.cnt[core])
     for a, b, n in zip(gpu["partner"][gi], H.partner[core], H.cnt[core]):

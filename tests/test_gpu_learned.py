@@ -222,14 +222,19 @@ def test_learned_needs_cleared_field(P):
         assert e.value.code == P.PRS_EINVAL
 
 
-def test_fused_network_matches_oracle_prediction(P, orc):
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fused_network_matches_oracle_prediction(P, orc, precision):
     """Realistic weights, no iteration (n_iter = 0): F_h is the sum of the
     network's initial force.  Agreement to the BF16 tie bound of the forward
-    pass: median per-sphere error tiny, maximum below 1e-3 of the largest."""
+    pass: median per-sphere error tiny, maximum below 1e-3 of the largest.
+    The single-precision pass standardises FP32 features, so its oracle gets
+    the FP32-rounded field the device sees."""
     rng = np.random.default_rng(5)
     w = TINY
     bed = W.make_bed(w)
     uh = [np.ascontiguousarray(a.numpy()) for a in fields_for(w, bed)]
+    if precision == 0:
+        uh = [a.astype(np.float32).astype(np.float64) for a in uh]
     p = oracle_params(orc, w, n_iter=0)
     feat = orc.learned_features(p, uh, bed.x, bed.u, bed.om)
     X = feat.reshape(-1, 16)
@@ -242,7 +247,7 @@ def test_fused_network_matches_oracle_prediction(P, orc):
     params[1024:1088] = rng.uniform(-0.2, 0.2, 64)
     F0 = orc.learned_initial_force(params.astype(np.float64), norm, feat, p.dt_f * p.alpha)
     ref = oracle_step(orc, w, bed, uh, F0, n_iter=0)
-    _, _, gpu = run_learned(P, w, 1, params, norm, n_iter=0)
+    _, _, gpu = run_learned(P, w, precision, params, norm, n_iter=0)
     assert gpu["st"]["iterations"] == 0
     err = np.linalg.norm(gpu["Fh"] - ref["Fh"], axis=1)
     scale = np.linalg.norm(ref["Fh"], axis=1).max()

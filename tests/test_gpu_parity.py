@@ -256,7 +256,13 @@ def test_step_parity(P, orc, precision, w):
     assert np.array_equal(gpu["partner"], ref["partner"])
     assert rel_err(gpu["dt"], ref["dt"]) < max(tol, 1e-10)
     assert rel_err(gpu["uin"], ref["uin"]) < max(tol, 1e-10)
-    assert gpu["st"]["pairs_last"] == int((ref["partner"][ref["count"] > 0] >= 0).sum()) // 2 or True
+    # sphere-sphere pairs and wall contacts at the last substep: the used
+    # slots of the oracle's history (each pair appears in both spheres')
+    used = np.arange(ref["partner"].shape[1])[None, :] < ref["count"][:, None]
+    pp = int(((ref["partner"] >= 0) & used).sum())
+    assert pp % 2 == 0 and pp > 0
+    assert gpu["st"]["pairs_last"] == pp // 2
+    assert gpu["st"]["wall_last"] == int(((ref["partner"] < 0) & used).sum())
 
 
 def test_two_steps_carry_history(P, orc):
