@@ -65,6 +65,7 @@ def lib():
         L.or_ib_forcing.argtypes = [P, dp, dp, dp, dp, dp, dp, C.c_int32, dp, dp, dp, dp, dp, dp,
                                     dp, ip, dp, dp, dp, dp]
         L.or_contacts.argtypes = [P, C.c_int32, dp, ip, C.c_int64, C.POINTER(C.c_int64)]
+        L.or_bed_flags.argtypes = [P, C.c_int32, dp, ip, C.POINTER(C.c_int64)]
         L.or_history_match.argtypes = [C.c_int32, ip, C.c_int32, ip, ip]
         L.or_history_match.restype = None
         L.or_dem.argtypes = [P, C.c_int32, dp, dp, dp, dp, dp, ip, dp, dp, ip, dp, dp]
@@ -199,6 +200,17 @@ def contacts(p: Params, x, cap=None):
     n_out = C.c_int64()
     rc = lib().or_contacts(C.byref(p), n, _d(x), _i(pairs), cap, C.byref(n_out))
     return rc, pairs[: min(n_out.value, cap)].copy(), n_out.value
+
+
+def bed_flags(p: Params, x):
+    """Bed (1) / flying (0) flag of every sphere and the bed count, by the
+    detection iteration of sec. 4.3.1 step (1); returns (rc, flags, n_bed)."""
+    x = _f64(x)
+    n = x.shape[0]
+    flags = np.zeros(n, dtype=np.int32)
+    nb = C.c_int64()
+    rc = lib().or_bed_flags(C.byref(p), n, _d(x), _i(flags), C.byref(nb))
+    return rc, flags, nb.value
 
 
 def history_match(old_ids, new_ids):

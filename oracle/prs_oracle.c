@@ -616,6 +616,64 @@ int or_contacts(const or_params *P, int32_t np, const double *x, int32_t *pairs,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Bed and flying particles (sec. 4.3.1, step (1)).  A particle in the       */
+/* bottom layer (centre below one diameter, y < 2R) is a bed particle, and   */
+/* so is every particle in contact with a bed particle, directly or through  */
+/* other bed particles; the rest are flying.  The detection is the paper's  */
+/* iteration: sweep over the particles, marking each one that is in the     */
+/* bottom layer or touches a particle already marked, and count the marks;  */
+/* repeat until the count stops changing.  Contacts are those of (A.3), the */
+/* partner lists of find_partners (the lists do not change during the      */
+/* sweeps, so they are formed once).                                        */
+/* flags[np] (out): 1 bed, 0 flying; *n_bed (out).  Return codes as         */
+/* or_contacts.                                                              */
+/* ------------------------------------------------------------------------ */
+int or_bed_flags(const or_params *P, int32_t np, const double *x, int32_t *flags, int64_t *n_bed)
+{
+    int rc = check_domain(P, np, x);
+    if (rc)
+        return rc;
+    or_cells C, *Cp = NULL;
+    if (P->use_cells) {
+        cells_build(P, np, x, &C);
+        Cp = &C;
+    }
+    int32_t *part = malloc(sizeof(int32_t) * OR_SLOTS * (np > 0 ? np : 1));
+    int32_t *npart = malloc(sizeof(int32_t) * (np > 0 ? np : 1));
+    for (int p = 0; p < np && rc == OR_OK; ++p) {
+        int k = find_partners(P, np, x, Cp, p, &part[OR_SLOTS * p]);
+        if (k < 0)
+            rc = OR_ECAPACITY;
+        npart[p] = k;
+    }
+    if (Cp)
+        cells_free(Cp);
+    int64_t N_bed = 0, N_temp;
+    if (rc == OR_OK) {
+        for (int p = 0; p < np; ++p)
+            flags[p] = 0;
+        do {
+            N_temp = N_bed;
+            N_bed = 0;
+            for (int i = 0; i < np; ++i) {
+                int bed = x[3 * i + 1] < 2.0 * P->R;
+                for (int s = 0; s < npart[i] && !bed; ++s) {
+                    int q = part[OR_SLOTS * i + s];
+                    if (q >= 0 && flags[q])
+                        bed = 1;
+                }
+                flags[i] = bed;
+                N_bed += bed;
+            }
+        } while (N_bed != N_temp);
+    }
+    *n_bed = N_bed;
+    free(part);
+    free(npart);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Contact history (sec. 3.4, memory optimisation).  M_temp holds the        */
 /* partners of p at the previous (sub)step with their u_in and delta_t; M_p  */
 /* the partners now.  For each partner now: if it is found in M_temp the     */
