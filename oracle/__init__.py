@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("n_sub", C.c_int32), ("k_n", C.c_double), ("e_n", C.c_double), ("mu", C.c_double),
         ("kt_ratio", C.c_double), ("dt_ratio", C.c_double),
         ("use_cells", C.c_int32),
+        ("contact_model", C.c_int32), ("t_c", C.c_double), ("e_t", C.c_double),
     ]
 
 
@@ -109,7 +110,7 @@ def make_params(**kw) -> Params:
     defaults = dict(h=0.1, R=0.5, rho_p=2.65, rho_f=1.0, g=(0.0, -1.0, 0.0), nl=314,
                     dt_f=8.27944e-4, alpha=1.0, n_iter=3, tol_mode=0, tol=1e-6, max_iter=10,
                     n_sub=20, k_n=1e5, e_n=0.9, mu=0.5, kt_ratio=2.0 / 7.0, dt_ratio=2.0 / 7.0,
-                    use_cells=0)
+                    use_cells=0, contact_model=0, t_c=10 * 8.27944e-4, e_t=0.39)
     defaults.update(kw)
     for k, v in defaults.items():
         if k == "g":

@@ -64,6 +64,11 @@ typedef struct {
     int32_t n_sub;       /* particle substeps per fluid step */
     double k_n, e_n, mu, kt_ratio, dt_ratio;
     int32_t use_cells;   /* 0: brute-force O(N^2) partner search; 1: cell list */
+    /* contact coefficients: 0 = fixed linear law (k_n, e_n, kt_ratio,
+     * dt_ratio); 1 = calibrated from the collision time t_c and the normal
+     * and tangential restitution coefficients e_n, e_t (see contact_coeffs) */
+    int32_t contact_model;
+    double t_c, e_t;
 } or_params;
 
 /* ------------------------------------------------------------------------ */
@@ -703,6 +708,35 @@ static double damping(double k, double e, double m_eff)
     return -2.0 * le * sqrt(m_eff * k) / sqrt(M_PI * M_PI + le * le);
 }
 
+/* Coefficients of one contact of effective mass m_eff.
+ * Model 0: the given stiffness k_n, d_n for restitution e_n, and the
+ * tangential pair as fixed fractions of the normal one.
+ * Model 1 (reading of the collision-time calibration of sec. 2.1 and 4.1,
+ * T_c = 10 dt_f, for the linear spring-dashpot): m x'' + d x' + k x = 0 from
+ * x = 0 with speed v lasts T_c = pi / sqrt(k/m - (d/2m)^2) and leaves with
+ * speed e v, e = exp(-d T_c / (2m)), so
+ *     d = -2 m ln(e) / T_c,   k = m (pi^2 + ln^2 e) / T_c^2,
+ * with m = m_eff and e = e_n for the normal pair, and m = (2/7) m_eff (the
+ * effective mass of a solid sphere's contact point under a tangential force)
+ * and e = e_t for the tangential pair: a contact that sticks throughout
+ * returns its tangential contact-point velocity with restitution e_t. */
+static void contact_coeffs(const or_params *P, double m_eff, double *kn, double *dn, double *kt,
+                           double *dt)
+{
+    if (P->contact_model == 1) {
+        double Tc = P->t_c, ln_n = log(P->e_n), ln_t = log(P->e_t), mt = (2.0 / 7.0) * m_eff;
+        *dn = -2.0 * m_eff * ln_n / Tc;
+        *kn = m_eff * (M_PI * M_PI + ln_n * ln_n) / (Tc * Tc);
+        *dt = -2.0 * mt * ln_t / Tc;
+        *kt = mt * (M_PI * M_PI + ln_t * ln_t) / (Tc * Tc);
+    } else {
+        *kn = P->k_n;
+        *dn = damping(P->k_n, P->e_n, m_eff);
+        *kt = P->kt_ratio * *kn;
+        *dt = P->dt_ratio * *dn;
+    }
+}
+
 static double dot3(const double a[3], const double b[3])
 {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
@@ -756,8 +790,8 @@ static void contact_force(const or_params *P, const double *x, const double *u, 
         ut[a] = ucp[a] - un * n[a];
     *uin_out = fabs(un);
 
-    const double kn = P->k_n, dn = damping(P->k_n, P->e_n, m_eff);
-    const double kt = P->kt_ratio * kn, dt = P->dt_ratio * dn;
+    double kn, dn, kt, dt;
+    contact_coeffs(P, m_eff, &kn, &dn, &kt, &dt);
     const double dtp = P->dt_f / P->n_sub;
 
     /* tangential displacement: rotate the stored one onto the tangent plane
