@@ -67,6 +67,9 @@ def lib():
                                     dp, ip, dp, dp, dp, dp]
         L.or_contacts.argtypes = [P, C.c_int32, dp, ip, C.c_int64, C.POINTER(C.c_int64)]
         L.or_bed_flags.argtypes = [P, C.c_int32, dp, ip, C.POINTER(C.c_int64)]
+        L.or_inner_fluid.argtypes = [P, dp, dp, dp, C.c_int32, dp, dp]
+        L.or_step_ex.argtypes = [P, C.c_double, C.c_int, dp, dp, dp, dp, dp, dp, C.c_int32, dp,
+                                 dp, dp, dp, ip, dp, dp, ip, dp, dp, dp, ip, dp, dp]
         L.or_history_match.argtypes = [C.c_int32, ip, C.c_int32, ip, ip]
         L.or_history_match.restype = None
         L.or_dem.argtypes = [P, C.c_int32, dp, dp, dp, dp, dp, ip, dp, dp, ip, dp, dp]
@@ -212,6 +215,43 @@ def bed_flags(p: Params, x):
     nb = C.c_int64()
     rc = lib().or_bed_flags(C.byref(p), n, _d(x), _i(flags), C.byref(nb))
     return rc, flags, nb.value
+
+
+def inner_fluid(p: Params, fields, x):
+    """Fluid velocity and its moment integrated over each sphere's volume by
+    the staggered nodes inside it, [n, 6] (int u dV, int r x u dV)."""
+    x = _f64(x)
+    g = [_f64(a) for a in fields]
+    out = np.zeros((x.shape[0], 6))
+    rc = lib().or_inner_fluid(C.byref(p), _d(g[0]), _d(g[1]), _d(g[2]), x.shape[0], _d(x),
+                              _d(out))
+    if rc:
+        raise RuntimeError(f"oracle inner_fluid failed with code {rc}")
+    return out
+
+
+def step_ex(p: Params, alpha, advance, uhat, f, x, u, om, hist: "History", F0=None,
+            inner_prev=None, want_inner=False):
+    """One step with a per-call forcing coefficient alpha, optionally the
+    inner-fluid term (inner_prev [n, 6]) and without the particle substeps
+    (advance = False); x, u, om, hist, f updated in place."""
+    for a in (x, u, om):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    uh = [_f64(a) for a in uhat]
+    F0, ip_ = _f64(F0), _f64(inner_prev)
+    n = x.shape[0]
+    Fh = np.zeros((n, 3))
+    Th = np.zeros((n, 3))
+    slip = np.zeros(max(p.n_iter, p.max_iter + 1, 1) + 1)
+    iters = C.c_int32()
+    inner = np.zeros((n, 6)) if want_inner else None
+    rc = lib().or_step_ex(C.byref(p), float(alpha), int(bool(advance)), _d(uh[0]), _d(uh[1]),
+                          _d(uh[2]), _d(f[0]), _d(f[1]), _d(f[2]), n, _d(x), _d(u), _d(om),
+                          _d(F0), _i(hist.partner), _d(hist.dt), _d(hist.uin), _i(hist.cnt),
+                          _d(Fh), _d(Th), _d(slip), C.byref(iters), _d(ip_), _d(inner))
+    it = iters.value
+    n_slip = it + 1 if p.tol_mode else max(it, 1)
+    return rc, dict(Fh=Fh, Th=Th, slip=slip[:n_slip].copy(), iters=it, inner=inner)
 
 
 def history_match(old_ids, new_ids):

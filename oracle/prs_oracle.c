@@ -958,3 +958,119 @@ int or_step(const or_params *P, const double *uhu, const double *uhv, const doub
         return rc;
     return or_dem(P, np, x, u, om, Fh, Th, hp, hd, hu, hc, NULL, NULL);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Fluid inside the spheres.  Reading of the hydrodynamic force of the       */
+/* direct-forcing method (sec. 2.1, eqs. 7-8): besides minus the marker       */
+/* forces, the force on a sphere includes the rate of change of the momentum  */
+/* of the fluid occupying its volume, rho_f d/dt int_{V_p} u dV (and         */
+/* rho_f d/dt int_{V_p} r x u dV for the torque).  The integrals are taken   */
+/* by the midpoint rule over the staggered nodes inside the sphere: node n   */
+/* of component c (wall faces and nodes outside the fluid excluded) with     */
+/* |x_n - x_p| < R (minimum image in x and z), each weighted h^3:            */
+/*   inner[p][c]     = h^3 sum_n u_c[n],                                     */
+/*   inner[p][3 + a] = h^3 sum_c sum_n eps_{a b c} r_b(x_n) u_c[n],          */
+/* r = x_n - x_p.  inner: [np][6].                                            */
+/* ------------------------------------------------------------------------ */
+int or_inner_fluid(const or_params *P, const double *gu, const double *gv, const double *gw,
+                   int32_t np, const double *x, double *inner)
+{
+    int rc = check_domain(P, np, x);
+    if (rc)
+        return rc;
+    const double *g[3] = {gu, gv, gw};
+    const double h = P->h, R = P->R, h3 = h * h * h;
+    const double Lx = P->nx * h, Lz = P->nz * h;
+    for (int p = 0; p < np; ++p) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            double o[3];
+            stagger_offset(c, o);
+            long lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = (long)floor((x[3 * p + a] - R) / h - o[a]) - 1;
+                hi[a] = (long)floor((x[3 * p + a] + R) / h - o[a]) + 1;
+            }
+            for (long k = lo[2]; k <= hi[2]; ++k)
+                for (long j = lo[1]; j <= hi[1]; ++j)
+                    for (long i = lo[0]; i <= hi[0]; ++i) {
+                        double r[3];
+                        r[0] = min_image((i + o[0]) * h - x[3 * p + 0], Lx);
+                        r[1] = (j + o[1]) * h - x[3 * p + 1];
+                        r[2] = min_image((k + o[2]) * h - x[3 * p + 2], Lz);
+                        if (!((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2] < R * R))
+                            continue;
+                        long nidx = node_index(P, c, i, j, k);
+                        if (nidx < 0)
+                            continue;
+                        double uc = g[c][nidx];
+                        acc[c] += uc;
+                        /* (r x e_c u_c): component a = eps_{a b c} r_b u_c */
+                        if (c == 0) {
+                            acc[4] += r[2] * uc;
+                            acc[5] -= r[1] * uc;
+                        } else if (c == 1) {
+                            acc[3] -= r[2] * uc;
+                            acc[5] += r[0] * uc;
+                        } else {
+                            acc[3] += r[1] * uc;
+                            acc[4] -= r[0] * uc;
+                        }
+                    }
+        }
+        for (int k = 0; k < 6; ++k)
+            inner[6 * p + k] = h3 * acc[k];
+    }
+    return OR_OK;
+}
+
+/* One step with the inner-fluid term and a per-call forcing coefficient
+ * (the alpha_k of the Runge-Kutta substep, eq. 4): the forcing with alpha
+ * dt_f; then F_h += rho_f (I_new - I_prev) / (alpha dt_f) and T_h likewise,
+ * with I_new the integrals of u** = u-hat + alpha dt_f f (the field after the
+ * forcing) over the spheres at their current positions and I_prev the
+ * caller's integrals of the previous call (inner_prev, [np][6], NULL: no
+ * inner-fluid term); inner_out (nullable) receives I_new.  advance = 0
+ * stops after the forcing (the spheres and the history are not moved, as in
+ * a Runge-Kutta substep that is not the last); otherwise the n_sub contact
+ * and Newton-Euler substeps follow. */
+int or_step_ex(const or_params *P0, double alpha, int advance, const double *uhu,
+               const double *uhv, const double *uhw, double *fu, double *fv, double *fw,
+               int32_t np, double *x, double *u, double *om, const double *F0, int32_t *hp,
+               double *hd, double *hu, int32_t *hc, double *Fh, double *Th, double *slip,
+               int32_t *iters, const double *inner_prev, double *inner_out)
+{
+    or_params P = *P0;
+    P.alpha = alpha;
+    int rc = check_domain(&P, np, x);
+    if (rc)
+        return rc;
+    const long nu = (long)P.wnz * P.ny * P.wnx, nv = (long)P.wnz * (P.ny + 1) * P.wnx;
+    double *us[3] = {NULL, NULL, NULL};
+    if (inner_prev || inner_out) {
+        us[0] = malloc(sizeof(double) * nu);
+        us[1] = malloc(sizeof(double) * nv);
+        us[2] = malloc(sizeof(double) * nu);
+    }
+    rc = or_ib_forcing(&P, uhu, uhv, uhw, fu, fv, fw, np, x, u, om, F0, Fh, Th, slip, iters, NULL,
+                       us[0], us[1], us[2]);
+    if (rc == OR_OK && (inner_prev || inner_out)) {
+        double *inner = malloc(sizeof(double) * 6 * (np > 0 ? np : 1));
+        rc = or_inner_fluid(&P, us[0], us[1], us[2], np, x, inner);
+        const double adt = P.alpha * P.dt_f;
+        for (int p = 0; p < np && rc == OR_OK && inner_prev; ++p)
+            for (int a = 0; a < 3; ++a) {
+                Fh[3 * p + a] += P.rho_f * (inner[6 * p + a] - inner_prev[6 * p + a]) / adt;
+                Th[3 * p + a] += P.rho_f * (inner[6 * p + 3 + a] - inner_prev[6 * p + 3 + a]) / adt;
+            }
+        if (inner_out)
+            memcpy(inner_out, inner, sizeof(double) * 6 * np);
+        free(inner);
+    }
+    for (int c = 0; c < 3; ++c)
+        free(us[c]);
+    if (rc || !advance)
+        return rc;
+    return or_dem(&P, np, x, u, om, Fh, Th, hp, hd, hu, hc, NULL, NULL);
+}
+
