@@ -83,7 +83,21 @@ typedef struct prs_params {
     double skin;         /* collision-search margin (>= 0), in length units */
     int32_t precision;   /* PRS_F32 or PRS_F64 */
     int32_t max_particles;
+    /* contact coefficients (sec. 2.1, 4.1):
+     *   PRS_CONTACT_FIXED: stiffness k_n, damping for restitution e_n with
+     *     the pair's effective mass (m/2 sphere-sphere, m sphere-wall), and
+     *     tangential k_t = kt_ratio k_n, d_t = dt_ratio d_n;
+     *   PRS_CONTACT_COLLISION_TIME: every pair's coefficients calibrated so
+     *     that a normal collision lasts t_c and restores e_n, and a sticking
+     *     tangential contact (effective mass 2/7 of the pair's) oscillates
+     *     with the same half-period and restores e_t: for mass m and
+     *     restitution e, d = -2 m ln(e) / t_c, k = m (pi^2 + ln^2 e) / t_c^2
+     *     (k_n, kt_ratio and dt_ratio unused). */
+    int32_t contact_model;
+    double t_c, e_t;
 } prs_params;
+
+enum { PRS_CONTACT_FIXED = 0, PRS_CONTACT_COLLISION_TIME = 1 };
 
 typedef struct prs_ctx prs_ctx;
 
@@ -166,6 +180,18 @@ int prs_spread(prs_ctx *ctx, void *stream, const double *x, int32_t n, const voi
 int prs_contacts(prs_ctx *ctx, void *stream, const double *x, int32_t n, int32_t *pairs,
                  int64_t cap, int64_t *n_out);
 
+/* Bed and flying spheres (sec. 4.3.1, step (1)): a sphere in the bottom
+ * layer (centre y < 2R) is a bed sphere, and so is every sphere in contact
+ * with a bed sphere (A.3: d^2 < (2R)^2, minimum image in x and z), directly
+ * or through a chain of contacts; all other spheres are flying.
+ * x: device double [n][3]; flags: device int8 [n] out, caller order (1 bed,
+ * 0 flying); n_bed: HOST int64 out, the number of bed spheres.  The same
+ * position checks as prs_contacts (PRS_EDOMAIN / PRS_ENONFINITE), and
+ * PRS_ECAPACITY when a sphere touches more than PRS_MAX_PP spheres.  The
+ * result does not depend on the order of the device's updates.  Synchronous. */
+int prs_bed_flags(prs_ctx *ctx, void *stream, const double *x, int32_t n, int8_t *flags,
+                  int64_t *n_bed);
+
 /* One particle-phase step (sec. 2.1 and 3): immersed-boundary forcing at the
  * current sphere state, then n_sub contact + Newton-Euler substeps of
  * dt_p = dt_f / n_sub with the hydrodynamic force and torque held fixed.
@@ -195,6 +221,53 @@ int prs_step_particles(prs_ctx *ctx, void *stream, const void *const uhat[3], vo
                        int zero_f, double *x, double *u, double *om, int32_t n,
                        const prs_history *hist, double *Fh, double *Th, const void *F0,
                        prs_stats *stats);
+
+/* The step with the options of a Runge-Kutta coupling (eqs. 3-6): the
+ * arguments of prs_step_particles in a struct, plus
+ *   alpha      : > 0: this call's forcing coefficient alpha_k of the
+ *                Runge-Kutta substep (the forcing uses alpha dt_f, eq. 4);
+ *                0: the context's alpha;
+ *   advance    : 0: the forcing only (F_h, T_h and f out; the spheres, their
+ *                velocities and the history keep their values: a substep
+ *                that is not the last); 1: the contact and Newton-Euler
+ *                substeps follow, as in prs_step_particles;
+ *   inner_prev : NULL, or [n][6] double: the previous call's integrals of
+ *                the fluid inside the spheres (see prs_inner_fluid); then
+ *                rho_f (I - I_prev) / (alpha dt_f) is added to F_h (first
+ *                three) and T_h (last three), with I the integrals of
+ *                u** = u-hat + alpha dt_f f after the forcing, over the spheres
+ *                at the positions this call starts from;
+ *   inner_out  : NULL, or [n][6] double out: I (required with inner_prev).
+ * Reading (the paper does not say where the particle substeps fall in the
+ * fluid's Runge-Kutta substeps): every substep forces the flow with its
+ * alpha_k, the particles are advanced once, in the last one. */
+typedef struct prs_step_args {
+    const void *const *uhat;   /* 3 grid fields, read only */
+    void *const *f;            /* 3 grid fields, in/out */
+    int32_t zero_f;
+    double *x, *u, *om;        /* [n][3] in/out */
+    int32_t n;
+    const prs_history *hist;
+    double *Fh, *Th;           /* [n][3] out */
+    const void *F0;            /* [n][n_markers][3] or NULL */
+    double alpha;
+    int32_t advance;
+    const double *inner_prev;
+    double *inner_out;
+} prs_step_args;
+int prs_step_particles_ex(prs_ctx *ctx, void *stream, const prs_step_args *args,
+                          prs_stats *stats);
+
+/* Fluid inside the spheres (the momentum term of the hydrodynamic force of
+ * the direct-forcing method, eqs. 7-8): for every sphere, by the midpoint rule
+ * over the staggered nodes inside it (|x_node - x_p| < R, minimum image in x
+ * and z; wall faces and nodes outside the fluid excluded), each weighted h^3:
+ *   inner[i][c]     = h^3 sum u_c[node]            (c = 0, 1, 2),
+ *   inner[i][3 + a] = h^3 sum (r x e_c u_c[node])_a, r = x_node - x_p.
+ * u: 3 grid fields; x: [n][3]; inner: device double [n][6] out.  Position
+ * checks as prs_contacts.  Synchronous. */
+int prs_inner_fluid(prs_ctx *ctx, void *stream, const void *const u[3], const double *x,
+                    int32_t n, double *inner);
 
 /* Per-phase device time of prs_step_particles, measured with HIP events
  * recorded on the caller's stream around each phase (milliseconds summed

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libprs.so")
 
 PRS_OK, PRS_EINVAL, PRS_ECAPACITY, PRS_EDOMAIN, PRS_ENONFINITE, PRS_EHIP, PRS_ESKIN = range(7)
 F32, F64 = 0, 1
+CONTACT_FIXED, CONTACT_COLLISION_TIME = 0, 1
 SLOTS = 14
 MAX_PP = 12
 WALL_BOTTOM, WALL_TOP = -1, -2
@@ -26,7 +27,9 @@ MAX_SLIP = 64
 _NAMES = {1: "EINVAL", 2: "ECAPACITY", 3: "EDOMAIN", 4: "ENONFINITE", 5: "EHIP", 6: "ESKIN"}
 
 EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_interpolate",
-           "prs_spread", "prs_contacts", "prs_step_particles", "prs_timing_enable",
+           "prs_spread", "prs_contacts", "prs_bed_flags", "prs_step_particles",
+           "prs_step_particles_ex", "prs_inner_fluid",
+           "prs_timing_enable",
            "prs_timing_read", "prs_mlp_create", "prs_mlp_destroy", "prs_mlp_last_error",
            "prs_mlp_get", "prs_mlp_forward", "prs_mlp_backward", "prs_mlp_adam",
            "prs_mlp_train_step", "prs_mlp_loss", "prs_mlp_standardize", "prs_mlp_fit_norm",
@@ -55,12 +58,21 @@ class Params(C.Structure):
         ("skin", C.c_double),
         ("precision", C.c_int32),
         ("max_particles", C.c_int32),
+        ("contact_model", C.c_int32), ("t_c", C.c_double), ("e_t", C.c_double),
     ]
 
 
 class _History(C.Structure):
     _fields_ = [("partner", C.c_void_p), ("delta_t", C.c_void_p), ("u_in", C.c_void_p),
                 ("count", C.c_void_p)]
+
+
+class StepArgs(C.Structure):
+    _fields_ = [("uhat", C.POINTER(C.c_void_p)), ("f", C.POINTER(C.c_void_p)),
+                ("zero_f", C.c_int32), ("x", C.c_void_p), ("u", C.c_void_p), ("om", C.c_void_p),
+                ("n", C.c_int32), ("hist", C.POINTER(_History)), ("Fh", C.c_void_p),
+                ("Th", C.c_void_p), ("F0", C.c_void_p), ("alpha", C.c_double),
+                ("advance", C.c_int32), ("inner_prev", C.c_void_p), ("inner_out", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -110,9 +122,12 @@ def lib():
         L.prs_interpolate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
         L.prs_spread.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int]
         L.prs_contacts.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.prs_bed_flags.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.prs_step_particles.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), C.c_int, vp, vp,
                                          vp, C.c_int32, C.POINTER(_History), vp, vp, vp,
                                          C.POINTER(Stats)]
+        L.prs_step_particles_ex.argtypes = [vp, vp, C.POINTER(StepArgs), C.POINTER(Stats)]
+        L.prs_inner_fluid.argtypes = [vp, vp, C.POINTER(vp), vp, C.c_int32, vp]
         L.prs_timing_enable.argtypes = [vp, C.c_int]
         L.prs_timing_read.argtypes = [vp, C.POINTER(Timing), C.c_int]
         L.prs_set_learned.argtypes = [vp, vp]
@@ -141,7 +156,8 @@ def make_params(**kw) -> Params:
     d = dict(h=0.1, radius=0.5, rho_p=2.65, rho_f=1.0, gravity=(0.0, -1.0, 0.0), n_markers=314,
              dt_f=8.27944e-4, alpha=1.0, n_iter=3, tol_mode=0, tol=1e-6, max_iter=10, n_sub=20,
              k_n=1e5, e_n=0.9, mu=0.5, kt_ratio=2.0 / 7.0, dt_ratio=2.0 / 7.0, skin=0.1,
-             precision=F64, max_particles=1)
+             precision=F64, max_particles=1, contact_model=CONTACT_FIXED, t_c=10 * 8.27944e-4,
+             e_t=0.39)
     d.update(kw)
     for k, v in d.items():
         if k == "gravity":
@@ -311,8 +327,26 @@ class Context:
         self._err(rc)
         return pairs[: n_out.value]
 
-    def step(self, uhat, f, x, u, om, hist: History, Fh=None, Th=None, F0=None, zero_f=False):
-        """One particle step in place (x, u, om, hist, f); returns (Fh, Th, stats)."""
+    def bed_flags(self, x):
+        """Bed (1) / flying (0) flag of every sphere (int8 device tensor, caller
+        order) and the number of bed spheres (prs_bed_flags)."""
+        import torch
+
+        n = x.shape[0]
+        self._chk_particles(n, x=x)
+        flags = torch.empty(n, dtype=torch.int8, device=x.device)
+        nb = C.c_int64()
+        self._err(lib().prs_bed_flags(self._h, _stream_ptr(), _ptr(x), n, _ptr(flags),
+                                      C.byref(nb)))
+        return flags, nb.value
+
+    def step(self, uhat, f, x, u, om, hist: History, Fh=None, Th=None, F0=None, zero_f=False,
+             alpha: float = 0.0, advance: bool = True, inner_prev=None, inner_out=None):
+        """One particle step in place (x, u, om, hist, f); returns (Fh, Th, stats).
+
+        alpha > 0: this call's forcing coefficient (a Runge-Kutta substep's
+        alpha_k); advance = False: the forcing only; inner_prev / inner_out
+        ([n, 6] float64): the inner-fluid term (prs_step_particles_ex)."""
         import torch
 
         n = x.shape[0]
@@ -330,15 +364,40 @@ class Context:
         self._chk_particles(n, Fh=Fh, Th=Th)
         if F0 is not None:
             self._chk(F0, (n, self.p.n_markers, 3), self.dtype, "F0")
+        for name, t in (("inner_prev", inner_prev), ("inner_out", inner_out)):
+            if t is not None:
+                self._chk(t, (n, 6), torch.float64, name)
         uh = (C.c_void_p * 3)(*[t.data_ptr() for t in uhat])
         ff = (C.c_void_p * 3)(*[t.data_ptr() for t in f])
         H = hist._c()
+        A = StepArgs()
+        A.uhat = C.cast(uh, C.POINTER(C.c_void_p))
+        A.f = C.cast(ff, C.POINTER(C.c_void_p))
+        A.zero_f = int(bool(zero_f))
+        A.x, A.u, A.om = _ptr(x), _ptr(u), _ptr(om)
+        A.n = n
+        A.hist = C.pointer(H)
+        A.Fh, A.Th, A.F0 = _ptr(Fh), _ptr(Th), _ptr(F0)
+        A.alpha = float(alpha)
+        A.advance = int(bool(advance))
+        A.inner_prev, A.inner_out = _ptr(inner_prev), _ptr(inner_out)
         st = Stats()
-        rc = lib().prs_step_particles(self._h, _stream_ptr(), uh, ff, int(bool(zero_f)), _ptr(x),
-                                      _ptr(u), _ptr(om), n, C.byref(H), _ptr(Fh), _ptr(Th),
-                                      _ptr(F0), C.byref(st))
+        rc = lib().prs_step_particles_ex(self._h, _stream_ptr(), C.byref(A), C.byref(st))
         self._err(rc)
         return Fh, Th, st.as_dict()
+
+    def inner_fluid(self, fields, x):
+        """Fluid velocity and its moment integrated over each sphere's volume,
+        [n, 6] float64 (prs_inner_fluid)."""
+        import torch
+
+        n = x.shape[0]
+        self._chk_fields(fields, "fields")
+        self._chk_particles(n, x=x)
+        out = torch.empty((n, 6), dtype=torch.float64, device=x.device)
+        g = (C.c_void_p * 3)(*[t.data_ptr() for t in fields])
+        self._err(lib().prs_inner_fluid(self._h, _stream_ptr(), g, _ptr(x), n, _ptr(out)))
+        return out
 
 
     def set_learned(self, mlp: Optional["Mlp"]):

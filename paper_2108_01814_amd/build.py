@@ -21,13 +21,15 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-# Per-file extra flags.  The contact kernels are built without FP contraction
-# so the contact test d^2 < (2R)^2 is evaluated exactly as written.
+# Per-file extra flags.  The contact kernels and the inner-fluid integrals are
+# built without FP contraction so the tests d^2 < (2R)^2 (contact, node inside
+# a sphere) are evaluated exactly as written.
 SOURCES = {
     "prs_ib.hip": [],
     "prs_sort.hip": [],
     "prs_dem.hip": ["-ffp-contract=off"],
     "prs_mlp.hip": [],
+    "prs_inner.hip": ["-ffp-contract=off"],
     "prs_capi.hip": [],
 }
 

@@ -184,12 +184,11 @@ int clear_field(prs_ctx *c, hipStream_t s, void *const f[3]) {
 //   target  : when set, alpha dt times every correction is accumulated into
 //             it (training samples).
 template <typename T>
-int run_forcing(prs_ctx *c, hipStream_t s, const void *const uhat[3], void *const f[3], int n,
-                const void *F0, bool need_den, bool learned, int n_fixed, float *target,
-                int &iters, int &n_slip, int &rejected, bool clear_f = false) {
+int run_forcing(prs_ctx *c, hipStream_t s, double adt, const void *const uhat[3],
+                void *const f[3], int n, const void *F0, bool need_den, bool learned, int n_fixed,
+                float *target, int &iters, int &n_slip, int &rejected, bool clear_f = false) {
   Scratch &S = c->S;
   const prs_params &q = c->p;
-  const double adt = q.alpha * q.dt_f;
   const T *uh[3] = {(const T *)uhat[0], (const T *)uhat[1], (const T *)uhat[2]};
   T *ff[3] = {(T *)f[0], (T *)f[1], (T *)f[2]};
   const T *fc[3] = {ff[0], ff[1], ff[2]};
@@ -321,9 +320,15 @@ int prs_create(const prs_params *p, prs_ctx **out) {
       q.n_iter > PRS_MAX_SLIP - 1)
     return bad("iter");
   if (q.tol_mode != 0 && q.tol_mode != 1) return bad("tol_mode");
-  if (q.n_sub < 0 || !(q.k_n > 0) || !(q.e_n > 0 && q.e_n <= 1) || !(q.mu >= 0) ||
-      !(q.kt_ratio > 0) || !(q.dt_ratio >= 0) || !(q.skin >= 0))
+  if (q.n_sub < 0 || !(q.e_n > 0 && q.e_n <= 1) || !(q.mu >= 0) || !(q.skin >= 0))
     return bad("contact");
+  if (q.contact_model == PRS_CONTACT_FIXED) {
+    if (!(q.k_n > 0) || !(q.kt_ratio > 0) || !(q.dt_ratio >= 0)) return bad("contact");
+  } else if (q.contact_model == PRS_CONTACT_COLLISION_TIME) {
+    if (!(q.t_c > 0) || !(q.e_t > 0 && q.e_t <= 1)) return bad("contact");
+  } else {
+    return bad("contact_model");
+  }
   if (q.precision != PRS_F32 && q.precision != PRS_F64) return bad("precision");
   if (q.max_particles < 0) return bad("max_particles");
   for (double gv : q.gravity)
@@ -370,11 +375,18 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     delete c;
     return PRS_EINVAL;
   }
-  // the interpolation brick of one sphere must fit in the periodic box
+  // the interpolation brick of one sphere must fit in the periodic box, and
+  // a spreading tile must see each sphere that reaches it through one
+  // periodic image only
   const int nb = brick_edge(q.radius, q.h);
-  if (q.nx <= nb || q.nz <= nb) {
-    delete c;
-    return PRS_EINVAL;
+  {
+    const int esz = q.precision == PRS_F64 ? 8 : 4;
+    const int reach = 2 * (int)std::ceil(q.radius / q.h - 1e-9) + 6;
+    if (q.nx <= nb || q.nz <= nb || q.nx < spread_tile_dim(esz, 0) + reach ||
+        q.nz < spread_tile_dim(esz, 2) + reach) {
+      delete c;
+      return PRS_EINVAL;
+    }
   }
   // every argument check above runs before the first HIP call
   (void)hipGetDevice(&c->device);
@@ -392,12 +404,25 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   M.I = 0.4 * M.m * R * R;
   const double V = (4.0 / 3.0) * M_PI * R * R * R;
   for (int a = 0; a < 3; ++a) M.fg[a] = (q.rho_p - q.rho_f) * V * q.gravity[a];
-  M.kn = q.k_n;
-  M.dn_pp = damping(q.k_n, q.e_n, 0.5 * M.m);
-  M.dn_pw = damping(q.k_n, q.e_n, M.m);
-  M.kt = q.kt_ratio * q.k_n;
-  M.dt_pp = q.dt_ratio * M.dn_pp;
-  M.dt_pw = q.dt_ratio * M.dn_pw;
+  if (q.contact_model == PRS_CONTACT_COLLISION_TIME) {
+    // a damped oscillator of mass m lasting t_c with restitution e
+    auto calib = [&](double m, double e, double &k, double &d) {
+      const double le = std::log(e);
+      d = -2.0 * m * le / q.t_c;
+      k = m * (M_PI * M_PI + le * le) / (q.t_c * q.t_c);
+    };
+    calib(0.5 * M.m, q.e_n, M.kn_pp, M.dn_pp);
+    calib(M.m, q.e_n, M.kn_pw, M.dn_pw);
+    calib((2.0 / 7.0) * 0.5 * M.m, q.e_t, M.kt_pp, M.dt_pp);
+    calib((2.0 / 7.0) * M.m, q.e_t, M.kt_pw, M.dt_pw);
+  } else {
+    M.kn_pp = M.kn_pw = q.k_n;
+    M.dn_pp = damping(q.k_n, q.e_n, 0.5 * M.m);
+    M.dn_pw = damping(q.k_n, q.e_n, M.m);
+    M.kt_pp = M.kt_pw = q.kt_ratio * q.k_n;
+    M.dt_pp = q.dt_ratio * M.dn_pp;
+    M.dt_pw = q.dt_ratio * M.dn_pw;
+  }
   M.mu = q.mu;
   M.dtp = q.n_sub > 0 ? q.dt_f / q.n_sub : 0.0;
   M.skin_half2 = 0.25 * q.skin * q.skin;
@@ -436,6 +461,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.slip_hist, PRS_MAX_SLIP + 1 + 256);
   rc |= alloc(c, &S.ncand, n);
   rc |= alloc(c, &S.cand, (size_t)kCandCap * n);
+  rc |= alloc(c, &S.bed, n);
   rc |= alloc(c, &S.ccount, n + 1);
   S.coffset = S.ccount;
   char *dF = nullptr;
@@ -458,6 +484,8 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.counters, 4);
   rc |= alloc(c, &S.templ, 3 * (size_t)q.n_markers);
   rc |= alloc(c, &S.lane_order, (size_t)q.n_markers);
+  rc |= alloc(c, &S.tm32, 8 * (size_t)q.n_markers);
+  rc |= alloc(c, &S.tm64, 4 * (size_t)q.n_markers);
   if (rc != PRS_OK) {
     prs_destroy(c);
     return PRS_EHIP;
@@ -467,7 +495,8 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     prs_destroy(c);
     return PRS_EHIP;
   }
-  if (launch_template(nullptr, S.templ, S.lane_order, q.n_markers) != hipSuccess ||
+  if (launch_template(nullptr, S.templ, S.tm32, S.tm64, S.lane_order, q.n_markers,
+                      q.radius / q.h) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     prs_destroy(c);
     return PRS_EHIP;
@@ -578,11 +607,55 @@ int prs_contacts(prs_ctx *c, void *stream, const double *x, int32_t n, int32_t *
   return PRS_OK;
 }
 
-int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void *const f[3],
-                       int zero_f, double *x, double *u, double *om, int32_t n,
-                       const prs_history *H, double *Fh, double *Th, const void *F0,
-                       prs_stats *stats) {
+int prs_bed_flags(prs_ctx *c, void *stream, const double *x, int32_t n, int8_t *flags,
+                  int64_t *n_bed) {
   if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!n_bed) return fail(c, PRS_EINVAL, "bed_flags: null n_bed");
+  if (n > 0 && (!x || !flags)) return fail(c, PRS_EINVAL, "bed_flags: null array");
+  *n_bed = 0;
+  if (n == 0) return PRS_OK;
+  hipStream_t s = as_stream(stream);
+  Scratch &S = c->S;
+  HIP_TRY(c, launch_reset_status(s, S));
+  HIP_TRY(c, launch_sort(s, S, c->C_touch, c->G, x, n, 0));
+  HIP_TRY(c, launch_gather_pos(s, S, c->G, x, n, nullptr, nullptr));
+  HIP_TRY(c, launch_bed_seed(s, S, c->C_touch, c->G, n));
+  // passes in groups of four between reads of the change count (a pass
+  // after the last change changes nothing); every pass marks at least one
+  // sphere until the last, so n + 1 passes always suffice
+  unsigned long long *host = reinterpret_cast<unsigned long long *>(c->host_pinned);
+  for (int64_t done = 0; done <= (int64_t)n; done += 4) {
+    HIP_TRY(c, hipMemsetAsync(S.counters + 3, 0, sizeof(unsigned long long), s));
+    for (int k = 0; k < 4; ++k) HIP_TRY(c, launch_bed_pass(s, S, n, S.counters + 3));
+    HIP_TRY(c, hipMemcpyAsync(host, S.counters + 3, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (host[0] == 0) break;
+  }
+  HIP_TRY(c, hipMemsetAsync(S.counters + 3, 0, sizeof(unsigned long long), s));
+  HIP_TRY(c, launch_bed_out(s, S, n, flags, S.counters + 3));
+  uint32_t st = 0;
+  HIP_TRY(c, hipMemcpyAsync(host, S.counters + 3, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(&st, S.status, sizeof st, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (int code = status_code(st)) return fail(c, code, "bed_flags: %s", status_text(st));
+  *n_bed = (int64_t)host[0];
+  return PRS_OK;
+}
+
+int prs_step_particles_ex(prs_ctx *c, void *stream, const prs_step_args *A, prs_stats *stats) {
+  if (!c) return PRS_EINVAL;
+  if (!A) return fail(c, PRS_EINVAL, "step: null arguments");
+  const void *const *uhat = A->uhat;
+  void *const *f = A->f;
+  const int zero_f = A->zero_f;
+  double *x = A->x, *u = A->u, *om = A->om;
+  const int32_t n = A->n;
+  const prs_history *H = A->hist;
+  double *Fh = A->Fh, *Th = A->Th;
+  const void *F0 = A->F0;
   if (int rc = check_n(c, n)) return rc;
   if (!uhat || !f || !uhat[0] || !uhat[1] || !uhat[2] || !f[0] || !f[1] || !f[2])
     return fail(c, PRS_EINVAL, "step: null field");
@@ -591,10 +664,15 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
     return fail(c, PRS_EINVAL, "step: null particle array");
   if (c->mlp && (!zero_f || F0))
     return fail(c, PRS_EINVAL, "step: a learned start needs zero_f = 1 and no F0");
+  if (!(A->alpha >= 0) || !std::isfinite(A->alpha))
+    return fail(c, PRS_EINVAL, "step: alpha must be finite and >= 0 (0: the context's)");
+  if (n > 0 && A->inner_prev && !A->inner_out)
+    return fail(c, PRS_EINVAL, "step: inner_prev needs inner_out");
   hipStream_t s = as_stream(stream);
   Scratch &S = c->S;
   const prs_params &q = c->p;
   const bool f64 = q.precision == PRS_F64;
+  const double adt = (A->alpha > 0 ? A->alpha : q.alpha) * q.dt_f;
 
   HIP_TRY(c, launch_reset_status(s, S));
   c->marks.clear();
@@ -622,24 +700,43 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
     const bool need_den = !zero_f || F0 != nullptr;
     const bool learned = c->mlp != nullptr;
     const int rc =
-        f64 ? run_forcing<double>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
+        f64 ? run_forcing<double>(c, s, adt, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
                                   n_slip, rejected, zero_f != 0)
-            : run_forcing<float>(c, s, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
+            : run_forcing<float>(c, s, adt, uhat, f, n, F0, need_den, learned, -1, nullptr, iters,
                                  n_slip, rejected, zero_f != 0);
     if (rc != PRS_OK) return rc;
     HIP_TRY(c, launch_ib_finish(s, S, c->G, n, q.rho_f));
+    if (A->inner_out) {
+      // fluid inside the spheres: rho_f d/dt int u** dV joins the force
+      if (f64) {
+        const double *uh[3] = {(const double *)uhat[0], (const double *)uhat[1],
+                               (const double *)uhat[2]};
+        const double *ff[3] = {(const double *)f[0], (const double *)f[1], (const double *)f[2]};
+        HIP_TRY(c, launch_inner_step<double>(s, c->G, S, uh, ff, adt, q.rho_f, n, A->inner_prev,
+                                             A->inner_out));
+      } else {
+        const float *uh[3] = {(const float *)uhat[0], (const float *)uhat[1],
+                              (const float *)uhat[2]};
+        const float *ff[3] = {(const float *)f[0], (const float *)f[1], (const float *)f[2]};
+        HIP_TRY(c, launch_inner_step<float>(s, c->G, S, uh, ff, adt, q.rho_f, n, A->inner_prev,
+                                            A->inner_out));
+      }
+    }
 
     // ---- contacts and Newton-Euler substeps ----
-    HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_candidates(s, S, c->C_step, c->G, n, 2.0 * q.radius + q.skin));
-    HIP_TRY(c, phase_end(c, s, kSearch));
-    for (int sub = 0; sub < q.n_sub; ++sub) {
+    const int n_sub = A->advance ? q.n_sub : 0;
+    if (n_sub > 0) {
       HIP_TRY(c, phase_begin(c, s));
-      HIP_TRY(c, launch_substep(s, S, c->G, c->M, n, sub & 1, sub == q.n_sub - 1));
+      HIP_TRY(c, launch_candidates(s, S, c->C_step, c->G, n, 2.0 * q.radius + q.skin));
+      HIP_TRY(c, phase_end(c, s, kSearch));
+    }
+    for (int sub = 0; sub < n_sub; ++sub) {
+      HIP_TRY(c, phase_begin(c, s));
+      HIP_TRY(c, launch_substep(s, S, c->G, c->M, n, sub & 1, sub == n_sub - 1));
       HIP_TRY(c, phase_end(c, s, kSubstep));
     }
     HIP_TRY(c, phase_begin(c, s));
-    HIP_TRY(c, launch_writeback(s, S, x, u, om, H, Fh, Th, n, q.n_sub & 1));
+    HIP_TRY(c, launch_writeback(s, S, x, u, om, H, Fh, Th, n, n_sub & 1));
     HIP_TRY(c, phase_end(c, s, kWriteback));
   }
 
@@ -661,6 +758,51 @@ int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void
     stats->flags = st;
   }
   if (int code = status_code(st)) return fail(c, code, "step: %s", status_text(st));
+  return PRS_OK;
+}
+
+int prs_step_particles(prs_ctx *c, void *stream, const void *const uhat[3], void *const f[3],
+                       int zero_f, double *x, double *u, double *om, int32_t n,
+                       const prs_history *H, double *Fh, double *Th, const void *F0,
+                       prs_stats *stats) {
+  prs_step_args A{};
+  A.uhat = uhat;
+  A.f = f;
+  A.zero_f = zero_f;
+  A.x = x;
+  A.u = u;
+  A.om = om;
+  A.n = n;
+  A.hist = H;
+  A.Fh = Fh;
+  A.Th = Th;
+  A.F0 = F0;
+  A.alpha = 0.0;
+  A.advance = 1;
+  return prs_step_particles_ex(c, stream, &A, stats);
+}
+
+int prs_inner_fluid(prs_ctx *c, void *stream, const void *const u[3], const double *x, int32_t n,
+                    double *inner) {
+  if (!c) return PRS_EINVAL;
+  if (int rc = check_n(c, n)) return rc;
+  if (!u || !u[0] || !u[1] || !u[2]) return fail(c, PRS_EINVAL, "inner_fluid: null field");
+  if (n > 0 && (!x || !inner)) return fail(c, PRS_EINVAL, "inner_fluid: null array");
+  if (n == 0) return PRS_OK;
+  hipStream_t s = as_stream(stream);
+  Scratch &S = c->S;
+  HIP_TRY(c, launch_reset_status(s, S));
+  if (c->p.precision == PRS_F64) {
+    const double *g[3] = {(const double *)u[0], (const double *)u[1], (const double *)u[2]};
+    HIP_TRY(c, launch_inner_fluid<double>(s, c->G, S, g, x, n, inner));
+  } else {
+    const float *g[3] = {(const float *)u[0], (const float *)u[1], (const float *)u[2]};
+    HIP_TRY(c, launch_inner_fluid<float>(s, c->G, S, g, x, n, inner));
+  }
+  uint32_t st = 0;
+  HIP_TRY(c, hipMemcpyAsync(&st, S.status, sizeof st, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (int code = status_code(st)) return fail(c, code, "inner_fluid: %s", status_text(st));
   return PRS_OK;
 }
 
@@ -715,10 +857,11 @@ int prs_forcing_samples(prs_ctx *c, void *stream, const void *const uhat[3], voi
       HIP_TRY(c, launch_interp_feat<float>(s, c->G, S, uh, n, feat));
     }
     // f = 0: the first iteration's slip is the zero-forcing slip
-    rc = f64 ? run_forcing<double>(c, s, uhat, f, n, nullptr, false, false, n_iter, target, iters,
-                                   n_slip, rejected)
-             : run_forcing<float>(c, s, uhat, f, n, nullptr, false, false, n_iter, target, iters,
-                                  n_slip, rejected);
+    const double adt = c->p.alpha * c->p.dt_f;
+    rc = f64 ? run_forcing<double>(c, s, adt, uhat, f, n, nullptr, false, false, n_iter, target,
+                                   iters, n_slip, rejected)
+             : run_forcing<float>(c, s, adt, uhat, f, n, nullptr, false, false, n_iter, target,
+                                  iters, n_slip, rejected);
     if (rc) return rc;
   }
   uint32_t st = 0;

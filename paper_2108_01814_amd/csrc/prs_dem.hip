@@ -192,8 +192,8 @@ __global__ __launch_bounds__(256) void k_substep(
       if (exist)
         for (int a = 0; a < 3; ++a) dprev[a] = o_dt[(o * 3 + a) * N + j];
       ContactOut c;
-      contact_law(M, R, M.kn, wall ? M.dn_pw : M.dn_pp, M.kt, wall ? M.dt_pw : M.dt_pp, nrm, xi,
-                  ucp, dprev, c);
+      contact_law(M, R, wall ? M.kn_pw : M.kn_pp, wall ? M.dn_pw : M.dn_pp,
+                  wall ? M.kt_pw : M.kt_pp, wall ? M.dt_pw : M.dt_pp, nrm, xi, ucp, dprev, c);
       if (nc < kSlots) {
         n_id[nc * N + j] = id;
         n_uin[nc * N + j] = exist ? o_uin[o * N + j] : c.un;
@@ -356,6 +356,82 @@ hipError_t launch_contact_list(hipStream_t s, const Scratch &S, const Cells &C, 
   hipLaunchKernelGGL(k_contact_list, dim3((n + 127) / 128), dim3(128), 0, s, C, G, S.start,
                      S.perm, S.inv_perm, S.xs[0], n, S.ccount, S.coffset, pairs, cap, S.status,
                      phase);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// bed and flying spheres (sec. 4.3.1, step (1))
+// ---------------------------------------------------------------------------
+// A sphere with its centre below one diameter is bed, and so is every sphere
+// touching a bed sphere, directly or through a chain of contacts.  The
+// touching partners (A.3) of every sphere are listed once (sorted indices,
+// [slot][n] in cand, counts in ncand); bed[] starts at the bottom layer and
+// passes over the spheres mark each one touching a marked partner, in place
+// (a mark made in a pass is seen by later reads of the same pass), until a
+// pass marks nothing.  Marks only ever go from 0 to 1, so the result is the
+// unique smallest closed set, whatever the order of the updates.
+__global__ void k_bed_seed(Cells C, Geom G, const int *__restrict__ start,
+                           const double *__restrict__ xs, int n, int *__restrict__ ncand,
+                           int *__restrict__ cand, int *__restrict__ bed, uint32_t *status) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double R = G.R;
+  int cnt = 0, all = 0;
+  for_each_near(C, G, start, xs, (size_t)n, 1, j, (2.0 * R) * (2.0 * R), [&](int k) {
+    if (cnt < kMaxPP) cand[cnt++ * (size_t)n + j] = k;
+    ++all;
+  });
+  if (all > kMaxPP) atomicOr(status, kFlagSlots);
+  ncand[j] = cnt;
+  bed[j] = xs[n + j] < 2.0 * R ? 1 : 0;
+}
+
+__global__ void k_bed_pass(int n, const int *__restrict__ ncand, const int *__restrict__ cand,
+                           int *bed, unsigned long long *changed) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int mark = 0;
+  if (j < n && !bed[j]) {
+    const int cnt = ncand[j];
+    for (int c = 0; c < cnt && !mark; ++c)
+      if (__atomic_load_n(&bed[cand[c * (size_t)n + j]], __ATOMIC_RELAXED)) mark = 1;
+    if (mark) __atomic_store_n(&bed[j], 1, __ATOMIC_RELAXED);
+  }
+  const int w = wave_sum_last(mark);
+  if ((threadIdx.x & 63) == 63 && w) atomicAdd(changed, (unsigned long long)w);
+}
+
+// flags[perm[j]] = bed[j]; counters[3] += bed spheres.
+__global__ void k_bed_out(int n, const int *__restrict__ perm, const int *__restrict__ bed,
+                          int8_t *__restrict__ flags, unsigned long long *count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  if (j < n) {
+    b = bed[j];
+    flags[perm[j]] = (int8_t)b;
+  }
+  const int w = wave_sum_last(b);
+  if ((threadIdx.x & 63) == 63 && w) atomicAdd(count, (unsigned long long)w);
+}
+
+hipError_t launch_bed_seed(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bed_seed, dim3((n + 127) / 128), dim3(128), 0, s, C, G, S.start, S.xs[0],
+                     n, S.ncand, S.cand, S.bed, S.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_bed_pass(hipStream_t s, const Scratch &S, int n, unsigned long long *changed) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bed_pass, dim3((n + 255) / 256), dim3(256), 0, s, n, S.ncand, S.cand,
+                     S.bed, changed);
+  return hipGetLastError();
+}
+
+hipError_t launch_bed_out(hipStream_t s, const Scratch &S, int n, int8_t *flags,
+                          unsigned long long *count) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bed_out, dim3((n + 255) / 256), dim3(256), 0, s, n, S.perm, S.bed, flags,
+                     count);
   return hipGetLastError();
 }
 

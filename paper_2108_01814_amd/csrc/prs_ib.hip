@@ -64,13 +64,33 @@ __global__ void k_lane_order(const double *t, int nl, int *order) {
   order[c0 + rank] = l;
 }
 
-hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl) {
+// Marker offsets in node units, (R / h) t_l: the double value, and its
+// single-precision rounding plus the remainder (also rounded).
+__global__ void k_marker_offsets(const double *t, int nl, double r_over_h, float *tm32,
+                                 double *tm64) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  for (int a = 0; a < 3; ++a) {
+    const double m = r_over_h * t[3 * l + a];
+    const float hi = (float)m;
+    tm32[8 * l + a] = hi;
+    tm32[8 * l + 4 + a] = (float)(m - (double)hi);
+    tm64[4 * l + a] = m;
+  }
+  tm32[8 * l + 3] = tm32[8 * l + 7] = 0.f;
+  tm64[4 * l + 3] = 0.0;
+}
+
+hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, int *lane_order,
+                           int nl, double r_over_h) {
   hipLaunchKernelGGL(k_template, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl);
   hipLaunchKernelGGL(k_lane_order, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl, lane_order);
+  hipLaunchKernelGGL(k_marker_offsets, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl, r_over_h,
+                     tm32, tm64);
   return hipGetLastError();
 }
 
-int brick_edge(double R, double h) { return (int)std::ceil(2.0 * R / h) + 5; }
+int brick_edge(double R, double h) { return 2 * brick_reach(R, h) + 2; }
 
 size_t brick_bytes(int nb, int esz) {
   return (size_t)nb * nb * (esz == 8 ? brick_pitch_c<double>(nb) : brick_pitch_c<float>(nb)) *
@@ -80,8 +100,9 @@ size_t brick_bytes(int nb, int esz) {
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
 size_t learned_lds_bytes(int nl) {
-  return kMlpLdsBytes + (size_t)block_for(nl) * (kMlpIn * sizeof(unsigned short) +
-                                                 kMlpUsed * sizeof(float));
+  const size_t per = (size_t)block_for(nl) * (kMlpIn * sizeof(unsigned short) +
+                                               kMlpUsed * sizeof(float));
+  return kMlpLdsBytes + ((per + 15) & ~(size_t)15) + kGeluTabN * sizeof(float4);
 }
 
 // ---------------------------------------------------------------------------
@@ -104,40 +125,35 @@ enum { kInterpMDF = 0, kInterpDen = 1, kInterpPlain = 2, kInterpFeat = 3, kInter
 //                    partial ||U_d - I[a]||^2.
 // MODE kInterpPlain: caller-order AoS positions; a only; writes U [n][nl][3]
 //                    and optionally U_d.
-// Brick rows loaded per lane before the LDS stores (measured on MI355X at
-// D/h = 10 with one field per pass: 1 is best for single precision (2: +5 %,
-// 4: +15 %), 2 for double (1 and 4: +7 %)).
-#ifndef PRS_BRICK_UNROLL_F32
-#define PRS_BRICK_UNROLL_F32 1
+//
+// The brick: nodes I_a - E .. I_a - E + nb - 1 along each axis a (I the
+// sphere centre's node, E = brick_reach), the same origin for the three
+// components (their staggering is in the stencil fractions).  Each
+// component's brick is nb * nb x-rows of nb values, padded to P elements
+// (16-byte chunks), loaded with one 16-byte load per chunk.  Rows outside the
+// fluid (and the wall faces of v) are zero; chunks that cross the periodic x
+// seam are loaded element by element.
+//
+// Chunk slots per lane of one component's brick: FP32 at D/h = 10 needs 3
+// (784 chunks, 320 lanes).
+#ifndef PRS_BRICK_SLOTS_F32
+#define PRS_BRICK_SLOTS_F32 3
 #endif
-#ifndef PRS_BRICK_UNROLL_F64
-#define PRS_BRICK_UNROLL_F64 2
-#endif
-#ifndef PRS_BRICK_ALL3_MAX_BYTES
-#define PRS_BRICK_ALL3_MAX_BYTES 0
-#endif
-// Chunks per lane held in registers by the software pipeline over the
-// components (0: no pipeline).  Single precision at D/h = 10 (3 chunks per
-// lane): 13.1 ms per pass with it, 13.9 without; 4 registers' worth of chunks
-// exceeds the 64 VGPRs of 8 waves per SIMD and is four times slower.
-#ifndef PRS_BRICK_PIPE_F32
-#define PRS_BRICK_PIPE_F32 3
-#endif
-#ifndef PRS_BRICK_PIPE_F64
-#define PRS_BRICK_PIPE_F64 0
+#ifndef PRS_BRICK_SLOTS_F64
+#define PRS_BRICK_SLOTS_F64 5
 #endif
 template <typename T>
-struct BrickUnroll {
-  static constexpr int value = sizeof(T) == 4 ? PRS_BRICK_UNROLL_F32 : PRS_BRICK_UNROLL_F64;
+struct BrickSlots {
+  static constexpr int value = sizeof(T) == 4 ? PRS_BRICK_SLOTS_F32 : PRS_BRICK_SLOTS_F64;
 };
 
-// NB > 0: brick edge known at compile time (the index arithmetic of the brick
-// loads then needs no integer divisions); NB == 0: runtime edge nb.
-template <typename T, int MODE, bool ALL3, int NB>
+// NB: brick edge known at compile time (14 at D/h = 10, 20 at D/h = 16) or 0
+// for the runtime edge nb.
+template <typename T, int MODE, int NB>
 __global__ __launch_bounds__(1024) void k_interp(
-    Geom G, const double *__restrict__ templ, const T *__restrict__ a0, const T *__restrict__ a1,
-    const T *__restrict__ a2, const T *__restrict__ b0, const T *__restrict__ b1,
-    const T *__restrict__ b2, double adt, const double *__restrict__ xs,
+    Geom G, const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ a0,
+    const T *__restrict__ a1, const T *__restrict__ a2, const T *__restrict__ b0,
+    const T *__restrict__ b1, const T *__restrict__ b2, double adt, const double *__restrict__ xs,
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
     double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la,
@@ -169,160 +185,149 @@ __global__ __launch_bounds__(1024) void k_interp(
       wp[a] = ws[a * N + p];
     }
   }
-  double rl[3] = {0, 0, 0}, X[3] = {0, 0, 0};
+  double rl[3] = {0, 0, 0};
   if (active)
-    for (int a = 0; a < 3; ++a) {
-      rl[a] = G.R * templ[3 * l + a];
-      X[a] = xp[a] + rl[a];
-    }
+    for (int a = 0; a < 3; ++a) rl[a] = G.R * templ[3 * l + a];
   const double Ud[3] = {up[0] + (wp[1] * rl[2] - wp[2] * rl[1]),
                         up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
   const T tadt = (T)adt;
-  const int nb2 = nb * nb;
   // An MDF pass over a nonzero f interpolates f alone and adds the step's
   // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
   // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
   // that interpolate u-hat record it in u0.
   const bool f_only = MODE == kInterpMDF && b0 != nullptr;
 
-  int lo[3][3];
-  for (int c = 0; c < 3; ++c)
-    for (int a = 0; a < 3; ++a) lo[c][a] = brick_lo(xp[a], G.R, G.inv_h, stagger(c, a)) - 1;
-  T U[3] = {(T)0, (T)0, (T)0};
-  // ALL3: the bricks of the three components are staged together; otherwise
-  // one component at a time.
-  // x-rows of the brick in chunks of VEC elements (16 bytes): one vector load
-  // per chunk, element-wise wrapped loads only for chunks that cross the
-  // periodic x boundary; rows padded to the pitch P in LDS
+  // the sphere's node, staggered fractions and brick origin
+  int I[3], lo[3];
+  T fo[3][2];
+  const int E = brick_reach(G.R, G.h);
+  for (int a = 0; a < 3; ++a) {
+    sphere_axis<T>(xp[a], G.inv_h, I[a], fo[a]);
+    lo[a] = I[a] - E;
+  }
+  // the marker's six axis stencils (three axes, two staggerings): brick
+  // index of the first node and the weights
+  int bs[3][2];
+  T w[3][2][3];
+  {
+    T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
+    if (active) MarkerOffset<T>::load(tm, l, mhi, mlo);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int c = stencil_axis<T>(fo[a][o], mhi[a], mlo[a], w[a][o]);
+        bs[a][o] = min(max(c - 1 + E, 0), nb - 3);
+      }
+  }
+
   constexpr int VEC = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
   const int P = brick_pitch_c<T>(nb);
   const int CPR = P / VEC;
-  const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
-  // chunk it of the brick of the components from c0 on (zero outside the
-  // fluid's rows)
-  auto load_chunk = [&](int c0, int it) {
-    vec_t v = (vec_t)(T)0;
+  const int per_comp = nb * nb * CPR;
+  // this lane's chunk slots, the same for the three components (their
+  // bricks share the origin): node plane k (wrapped), row offset j nx, first
+  // x node x0, and flags (bit 0: row inside the fluid for u and w, bit 1: for
+  // v, bit 2: the chunk crosses the periodic x seam, bit 3: slot in use)
+  constexpr int kSlots = BrickSlots<T>::value;
+  int sK[kSlots], sJ[kSlots], sX[kSlots], sF[kSlots];
+#pragma unroll
+  for (int u = 0; u < kSlots; ++u) {
+    const int it = threadIdx.x + u * blockDim.x;
     const int row = it / CPR, ch = it - row * CPR;
-    const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
-    const int rr = row - cc * nb2;
-    const int bz = rr / nb, by = rr - bz * nb;
-    const int j = lo[c][1] + by;
-    if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
-      const int k = wrap_once(lo[c][2] + bz, G.nz);
-      const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
-      const int x0 = lo[c][0] + ch * VEC;
-      const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
-                            : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
-      if (x0 >= 0 && x0 + VEC <= G.nx) {
-        __builtin_memcpy(&v, Sp + x0, sizeof(vec_t));
+    const int bz = row / nb, by = row - bz * nb;
+    const int j = lo[1] + by;
+    const int x0 = lo[0] + ch * VEC;
+    sK[u] = wrap_once(lo[2] + bz, G.nz);
+    sJ[u] = j * G.nx;
+    sX[u] = x0;
+    sF[u] = (j >= 0 && j <= G.ny - 1 ? 1 : 0) | (j >= 1 && j <= G.ny - 1 ? 2 : 0) |
+            (x0 < 0 || x0 + VEC > G.nx ? 4 : 0) | (it < per_comp ? 8 : 0);
+  }
+  const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
+  auto load_slot = [&](int c, int u) {
+    vec_t v = (vec_t)(T)0;
+    const int fl = sF[u];
+    if ((fl & 8) && (fl & (c == 1 ? 2 : 1))) {
+      const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
+      const T *rowp = Sp + ((size_t)sK[u] * (size_t)nyc_[c] * (size_t)G.nx + (size_t)sJ[u]);
+      if (!(fl & 4)) {
+        __builtin_memcpy(&v, rowp + sX[u], sizeof(vec_t));
       } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) v[e] = Sp[wrap_once(x0 + e, G.nx)];
+        for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(sX[u] + e, G.nx)];
       }
     }
     return v;
   };
-  auto store_chunk = [&](int it, vec_t v) {
-    const int row = it / CPR, ch = it - row * CPR;
-    *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
-  };
-  // Software pipeline over the components when a lane holds at most kPipe
-  // chunks of one brick: the next component's chunks are loaded into
-  // registers while the current one's stencils run.
-  // (MDF passes only: the other modes hold more registers of their own)
-  constexpr int kPipeCfg =
-      MODE != kInterpMDF ? 0 : (sizeof(T) == 4 ? PRS_BRICK_PIPE_F32 : PRS_BRICK_PIPE_F64);
-  constexpr int kPipe = kPipeCfg > 0 ? kPipeCfg : 1;
-  const int per_comp = nb2 * CPR;
-  const bool pipe = !ALL3 && kPipeCfg > 0 && per_comp <= kPipe * (int)blockDim.x;
-  vec_t nxt[kPipe];
-  auto issue = [&](int c) {
-#pragma unroll
-    for (int u = 0; u < kPipe; ++u) {
-      const int it = threadIdx.x + u * blockDim.x;
-      nxt[u] = it < per_comp ? load_chunk(c, it) : (vec_t)(T)0;
+  auto store_slot = [&](int u, vec_t v) {
+    const int it = threadIdx.x + u * blockDim.x;
+    if (it < per_comp) {
+      const int row = it / CPR, ch = it - row * CPR;
+      *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
     }
   };
-  if (pipe) issue(0);
-  for (int pass = 0; pass < (ALL3 ? 1 : 3); ++pass) {
-    const int c0 = ALL3 ? 0 : pass, nc = ALL3 ? 3 : 1;
-    __syncthreads();   // the previous pass's brick is no longer read
+  T U[3] = {(T)0, (T)0, (T)0};
+  // software pipeline (when the lane's slots cover the brick): the next
+  // component's chunks are loaded into registers while the current
+  // component's stencils run; otherwise (few markers per sphere) each
+  // component's brick is loaded in rounds of blockDim chunks
+  const bool pipe = per_comp <= kSlots * (int)blockDim.x;
+  vec_t nxt[kSlots];
+  if (pipe) {
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(0, u);
+  }
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();   // the previous component's brick is no longer read
     if (pipe) {
 #pragma unroll
-      for (int u = 0; u < kPipe; ++u) {
-        const int it = threadIdx.x + u * blockDim.x;
-        if (it < per_comp) store_chunk(it, nxt[u]);
+      for (int u = 0; u < kSlots; ++u) store_slot(u, nxt[u]);
+      if (c < 2) {
+#pragma unroll
+        for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(c + 1, u);
       }
-      if (pass < 2) issue(pass + 1);
     } else {
-      // (load_chunk's loads written out in the loop: built on the lambda,
-      // this loop measured 9 % slower)
-      const int nitems = nc * per_comp;
-      constexpr int kBrickUnroll = BrickUnroll<T>::value;
-      for (int it0 = threadIdx.x; it0 < nitems; it0 += blockDim.x * kBrickUnroll) {
-        vec_t v[kBrickUnroll];
+      const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
+      for (int it = threadIdx.x; it < per_comp; it += blockDim.x) {
+        const int row = it / CPR, ch = it - row * CPR;
+        const int bz = row / nb, by = row - bz * nb;
+        const int j = lo[1] + by, x0 = lo[0] + ch * VEC;
+        vec_t v = (vec_t)(T)0;
+        if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
+          const int k = wrap_once(lo[2] + bz, G.nz);
+          const T *rowp = Sp + ((size_t)k * (size_t)nyc_[c] + (size_t)j) * (size_t)G.nx;
+          if (x0 >= 0 && x0 + VEC <= G.nx) {
+            __builtin_memcpy(&v, rowp + x0, sizeof(vec_t));
+          } else {
 #pragma unroll
-        for (int u = 0; u < kBrickUnroll; ++u) {
-          const int it = it0 + u * blockDim.x;
-          v[u] = (vec_t)(T)0;
-          if (it < nitems) {
-            const int row = it / CPR, ch = it - row * CPR;
-            const int cc = ALL3 ? row / nb2 : 0, c = c0 + cc;
-            const int rr = row - cc * nb2;
-            const int bz = rr / nb, by = rr - bz * nb;
-            const int j = lo[c][1] + by;
-            if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
-              const int k = wrap_once(lo[c][2] + bz, G.nz);
-              const size_t rowg = ((size_t)k * nyc_[c] + j) * G.nx;
-              const int x0 = lo[c][0] + ch * VEC;
-              const T *Sp = (f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2))
-                                    : (c == 0 ? a0 : (c == 1 ? a1 : a2))) + rowg;
-              if (x0 >= 0 && x0 + VEC <= G.nx) {
-                __builtin_memcpy(&v[u], Sp + x0, sizeof(vec_t));
-              } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) v[u][e] = Sp[wrap_once(x0 + e, G.nx)];
-              }
-            }
+            for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(x0 + e, G.nx)];
           }
         }
-#pragma unroll
-        for (int u = 0; u < kBrickUnroll; ++u) {
-          const int it = it0 + u * blockDim.x;
-          if (it < nitems) {
-            const int row = it / CPR, ch = it - row * CPR;
-            *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v[u];
-          }
-        }
+        *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
       }
     }
     __syncthreads();
     if (active) {
-      for (int cc = 0; cc < nc; ++cc) {
-        const int c = c0 + cc;
-        // the 27-point sum contracted separably (x, then y, then z)
-        Stencil<T> S;
-        make_stencil<T>(G, c, X, S);
-        const int b0 = min(max(S.ic[0] - 1 - lo[c][0], 0), nb - 3);
-        const int b1 = min(max(S.ic[1] - 1 - lo[c][1], 0), nb - 3);
-        const int b2 = min(max(S.ic[2] - 1 - lo[c][2], 0), nb - 3);
-        const T *bk = brick + cc * nb2 * P;
-        T zsum = 0;
+      // the 27-point sum contracted separably (x, then y, then z)
+      const int ox = stag(c, 0), oy = stag(c, 1), oz = stag(c, 2);
+      const T *bk = brick + ((bs[2][oz] * nb + bs[1][oy]) * P + bs[0][ox]);
+      const T *wx = w[0][ox], *wy = w[1][oy], *wz = w[2][oz];
+      T zsum = 0;
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          T ysum = 0;
+      for (int kk = 0; kk < 3; ++kk) {
+        T ysum = 0;
 #pragma unroll
-          for (int jj = 0; jj < 3; ++jj) {
-            const T *row = bk + ((b2 + kk) * nb + (b1 + jj)) * P + b0;
-            const T xsum = row[0] * S.w[0][0] + row[1] * S.w[0][1] + row[2] * S.w[0][2];
-            ysum += S.w[1][jj] * xsum;
-          }
-          zsum += S.w[2][kk] * ysum;
+        for (int jj = 0; jj < 3; ++jj) {
+          const T *row = bk + (kk * nb + jj) * P;
+          const T xsum = fma(row[2], wx[2], fma(row[1], wx[1], row[0] * wx[0]));
+          ysum = fma(wy[jj], xsum, ysum);
         }
-        U[c] = zsum;
+        zsum = fma(wz[kk], ysum, zsum);
       }
+      U[c] = zsum;
     }
   }
 
@@ -370,8 +375,11 @@ __global__ __launch_bounds__(1024) void k_interp(
     // 4q .. 4q+3 of marker r of the tile (tile = 16 consecutive lanes)
     bf16x4 *fl = reinterpret_cast<bf16x4 *>(smem_raw + kMlpLdsBytes);
     float *yl = reinterpret_cast<float *>(fl + blockDim.x * (kMlpIn / 4));
+    float4 *gtab = reinterpret_cast<float4 *>(yl + blockDim.x * kMlpUsed);
     __syncthreads();   // the brick is no longer read
     mlp_stage(L, la.wbf, la.master, false);
+    for (int i = threadIdx.x; i < kGeluTabN; i += blockDim.x)
+      gtab[i] = reinterpret_cast<const float4 *>(la.gelu_tab)[i];
     {
       const int tile = threadIdx.x >> 4, r = threadIdx.x & 15;
       for (int q = 0; q < kMlpIn / 4; ++q) {
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     for (int t = 0; t < 4; ++t) {
       const int tile = 4 * wave + t;
       MlpFwd s;
-      mlp_forward_tile(L, fl[tile * 64 + lane], s);
+      mlp_forward_tile(L, fl[tile * 64 + lane], s, GeluTable{gtab});
       if (q == 0)
         for (int i = 0; i < kMlpUsed; ++i) yl[(16 * tile + r) * kMlpUsed + i] = s.y[i];
     }
@@ -455,50 +463,31 @@ __global__ __launch_bounds__(1024) void k_interp(
 }
 
 // Launch k_interp with the brick edge as a compile-time constant when it is
-// one of the common sizes (D/h = 10 -> 15, D/h = 16 -> 21).
-template <typename T, int MODE, bool ALL3>
-void launch_interp_nb(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Geom &G,
-                      const double *templ, const T *a0, const T *a1, const T *a2, const T *b0,
-                      const T *b1, const T *b2, double adt, const double *xs, const double *us,
-                      const double *ws, int n, int nb, T *out, T *out2, double *slip_part,
-                      double *ft_part, const int *order, const LearnArgs &la,
-                      float *vmax_out, T *u0) {
-  if (nb == 15)
-    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 15>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out, u0);
-  else if (nb == 21)
-    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 21>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out, u0);
-  else
-    hipLaunchKernelGGL((k_interp<T, MODE, ALL3, 0>), grid, block, lds, s, G, templ, a0, a1, a2,
-                       b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la,
-                       vmax_out, u0);
-}
-
+// one of the common sizes (D/h = 10 -> 14, D/h = 16 -> 20).
 template <typename T, int MODE>
-hipError_t launch_interp_any(hipStream_t s, const Geom &G, const double *templ, const T *a0,
+hipError_t launch_interp_any(hipStream_t s, const Geom &G, const Scratch &S, const T *a0,
                              const T *a1, const T *a2, const T *b0, const T *b1, const T *b2,
                              double adt, const double *xs, const double *us, const double *ws,
                              int n, T *out, T *out2, double *slip_part, double *ft_part,
-                             const int *order, const LearnArgs &la = LearnArgs{},
-                             float *vmax_out = nullptr, T *u0 = nullptr) {
+                             const LearnArgs &la = LearnArgs{}, float *vmax_out = nullptr,
+                             T *u0 = nullptr) {
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
-  const size_t one = sizeof(T) * nb * nb * brick_pitch_c<T>(nb);
-  const bool all3 = 3 * one <= PRS_BRICK_ALL3_MAX_BYTES;
   const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
-  size_t lds = all3 ? 3 * one : one;
+  size_t lds = brick_bytes(nb, sizeof(T));
   if (MODE == kInterpLearned) lds = std::max(lds, learned_lds_bytes(G.nl));
-  if (all3)
-    launch_interp_nb<T, MODE, true>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                    xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out,
-                                    u0);
+  const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
+#define PRS_LAUNCH_INTERP(NBV)                                                                 \
+  hipLaunchKernelGGL((k_interp<T, MODE, NBV>), grid, block, lds, s, G, S.templ, tm, a0, a1, a2, \
+                     b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part,        \
+                     S.lane_order, la, vmax_out, u0)
+  if (nb == 14)
+    PRS_LAUNCH_INTERP(14);
+  else if (nb == 20)
+    PRS_LAUNCH_INTERP(20);
   else
-    launch_interp_nb<T, MODE, false>(grid, block, lds, s, G, templ, a0, a1, a2, b0, b1, b2, adt,
-                                     xs, us, ws, n, nb, out, out2, slip_part, ft_part, order, la, vmax_out,
-                                    u0);
+    PRS_LAUNCH_INTERP(0);
+#undef PRS_LAUNCH_INTERP
   return hipGetLastError();
 }
 
@@ -506,23 +495,22 @@ template <typename T>
 hipError_t launch_interp_plain(hipStream_t s, const Geom &G, const Scratch &S, const T *gu,
                                const T *gv, const T *gw, const double *x, const double *up,
                                const double *om, int n, T *U, T *Ud) {
-  return launch_interp_any<T, kInterpPlain>(s, G, S.templ, gu, gv, gw, nullptr, nullptr, nullptr,
-                                            0.0, x, up, om, n, U, Ud, nullptr, nullptr,
-                                            S.lane_order);
+  return launch_interp_any<T, kInterpPlain>(s, G, S, gu, gv, gw, nullptr, nullptr, nullptr, 0.0,
+                                            x, up, om, n, U, Ud, nullptr, nullptr);
 }
 
 template <typename T>
 hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
                              const T *f[3], int n, double adt, int den_only) {
   if (den_only)
-    return launch_interp_any<T, kInterpDen>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+    return launch_interp_any<T, kInterpDen>(s, G, S, uh[0], uh[1], uh[2], nullptr, nullptr,
                                             nullptr, adt, S.xs[0], S.us[0], S.ws[0], n, nullptr,
-                                            nullptr, S.slip_part, nullptr, S.lane_order,
-                                            LearnArgs{}, nullptr, (T *)S.u0);
-  return launch_interp_any<T, kInterpMDF>(s, G, S.templ, uh[0], uh[1], uh[2], f[0], f[1], f[2],
-                                          adt, S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
-                                          S.slip_part, S.ft_part, S.lane_order, LearnArgs{},
-                                          S.vmax, (T *)S.u0);
+                                            nullptr, S.slip_part, nullptr, LearnArgs{}, nullptr,
+                                            (T *)S.u0);
+  return launch_interp_any<T, kInterpMDF>(s, G, S, uh[0], uh[1], uh[2], f[0], f[1], f[2], adt,
+                                          S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
+                                          S.slip_part, S.ft_part, LearnArgs{}, S.vmax,
+                                          (T *)S.u0);
 }
 
 template <typename T>
@@ -531,18 +519,18 @@ hipError_t launch_interp_feat(hipStream_t s, const Geom &G, const Scratch &S, co
   LearnArgs la{};
   la.perm = S.perm;
   la.feat = feat;
-  return launch_interp_any<T, kInterpFeat>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+  return launch_interp_any<T, kInterpFeat>(s, G, S, uh[0], uh[1], uh[2], nullptr, nullptr,
                                            nullptr, 0.0, S.xs[0], S.us[0], S.ws[0], n, nullptr,
-                                           nullptr, S.slip_part, nullptr, S.lane_order, la);
+                                           nullptr, S.slip_part, nullptr, la);
 }
 
 template <typename T>
 hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
                                  int n, double adt, const LearnArgs &la) {
-  return launch_interp_any<T, kInterpLearned>(s, G, S.templ, uh[0], uh[1], uh[2], nullptr, nullptr,
+  return launch_interp_any<T, kInterpLearned>(s, G, S, uh[0], uh[1], uh[2], nullptr, nullptr,
                                               nullptr, adt, S.xs[0], S.us[0], S.ws[0], n,
-                                              (T *)S.dF, nullptr, S.slip_part, S.ft_part,
-                                              S.lane_order, la, S.vmax, (T *)S.u0);
+                                              (T *)S.dF, nullptr, S.slip_part, S.ft_part, la,
+                                              S.vmax, (T *)S.u0);
 }
 
 // target[caller marker][c] += adt * dF[c][sorted marker]
@@ -603,7 +591,7 @@ template hipError_t launch_accum_target<double>(hipStream_t, const Geom &, const
 #define PRS_TILE_F32 16, 8, 16
 #endif
 #ifndef PRS_TILE_F64
-#define PRS_TILE_F64 16, 8, 16
+#define PRS_TILE_F64 16, 8, 8
 #endif
 #ifndef PRS_TILE_THREADS
 #define PRS_TILE_THREADS 512
@@ -639,31 +627,61 @@ struct TileAcc<float> {
   using type = int;
 };
 
-// Row pitch of the LDS accumulators: TX + PRS_SPREAD_PAD entries (one pad
-// entry spreads the rows of a tile over the banks: -8 % spreading time at
-// D/h = 10 on MI355X; two measured no better than none).
-#ifndef PRS_SPREAD_PAD
-#define PRS_SPREAD_PAD 1
-#endif
+// Guard band of the accumulators: two nodes on every side of the tile.  A
+// marker's component is accumulated when its 3-node stencil meets the tile
+// along every axis, so its nodes lie within the band, and all 27 adds run
+// without per-node tests (the band's sums are discarded).
+constexpr int kGuard = 2;
 
 constexpr int kTileCand = 256;     // spheres gathered by one tile
 constexpr int kTileThreads = PRS_TILE_THREADS;
-constexpr int kTileList = 2048;    // culled markers buffered before accumulation
+constexpr int kTileList = 1024;    // culled markers buffered before accumulation
 static_assert(kTileThreads >= kTileCand && kTileCand % 64 == 0, "one scan lane per candidate");
 static_assert(kTileList >= 2 * kTileThreads, "a round must fit after a flush check");
 static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
 
-// One marker's contribution to a tile: weights of the three staggered
-// stencils, in-tile masks, and LDS atomic adds of value * weight * dV / h^3.
+// A candidate sphere of a tile: the offset of its centre node from the tile's
+// first node plus the guard (periodic axes by minimum image about the tile
+// centre), and its staggered fractions (sphere_axis).
+template <typename T>
+struct TileCand {
+  int d[3];
+  T fo[3][2];
+};
+
+template <typename T, int TX, int TY, int TZ>
+__device__ inline void tile_cand(const Geom &G, double x, double y, double z, int i0, int j0,
+                                 int k0, int d[3], T fo[3][2]) {
+  int I[3];
+  sphere_axis<T>(x, G.inv_h, I[0], fo[0]);
+  sphere_axis<T>(y, G.inv_h, I[1], fo[1]);
+  sphere_axis<T>(z, G.inv_h, I[2], fo[2]);
+  const int n[3] = {G.nx, 0, G.nz}, t0[3] = {i0, j0, k0}, tl[3] = {TX, TY, TZ};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int dd = I[a] - t0[a];
+    if (a != 1) {
+      // minimum image about the tile centre
+      const int rel2 = 2 * dd - tl[a];
+      if (rel2 >= n[a]) dd -= n[a];
+      else if (rel2 < -n[a]) dd += n[a];
+    }
+    d[a] = dd + kGuard;
+  }
+}
+
+// One marker's contribution to a tile: the six axis stencils, and for each
+// component whose stencil meets the tile, its 27 adds of
+// value * weight * dV / h^3 into the guard-banded accumulator.
 // scale: dV / h^3 (floating-point accumulators) or dV / h^3 / unit (fixed point).
-template <typename T, int SRC, int TX, int TY, int TZ, int PX>
-__device__ inline void spread_marker(const Geom &G, const double X[3], const T *__restrict__ src,
-                                     const int *__restrict__ perm, int k, int l, size_t M,
-                                     T scale, int i0, int j0, int k0,
-                                     typename TileAcc<T>::type *acc) {
+template <typename T, int SRC, int TX, int TY, int TZ>
+__device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3][2],
+                                    const T *__restrict__ tm, const T *__restrict__ src,
+                                    const int *__restrict__ perm, int k, int l, size_t M, T scale,
+                                    typename TileAcc<T>::type *acc) {
   using A_t = typename TileAcc<T>::type;
-  constexpr int NODES = TX * TY * TZ, NODES_P = PX * TY * TZ;
-  (void)NODES;
+  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
+  constexpr int NODES_P = PX * PY * PZ;
   T v[3];
   if (SRC == 0) {
     const size_t m = (size_t)k * G.nl + l;
@@ -672,59 +690,37 @@ __device__ inline void spread_marker(const Geom &G, const double X[3], const T *
     const size_t m = (size_t)perm[k] * G.nl + l;
     for (int c = 0; c < 3; ++c) v[c] = src[3 * m + c];
   }
-  // Per axis only two stencils exist: nodes on cell faces (stagger 0, the
-  // component along that axis) and at cell centres (stagger 1/2, the other
-  // two).  Evaluate each once, with its local tile indices and in-tile mask.
-  // (Adding zero-weight terms at clamped indices instead of masking, for all
-  // nodes or for the x-nodes of a row, measured slower: the extra LDS atomics
-  // cost more than the branches they save.)
+  T mhi[3], mlo[3];
+  MarkerOffset<T>::load(tm, l, mhi, mlo);
+  int b[3][2];
   T w[3][2][3];
-  int li[3][2][3];
-  unsigned msk[3][2];
-  const int tlen[3] = {TX, TY, TZ}, t0[3] = {i0, j0, k0};
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-      int ic;
-      kernel3<T>(X[a] * G.inv_h - (o ? 0.5 : 0.0), ic, w[a][o]);
-      unsigned m = 0;
-      for (int t = 0; t < 3; ++t) {
-        int node = ic - 1 + t;
-        if (a == 0) node = wrap_once(node, G.nx);
-        if (a == 2) node = wrap_once(node, G.nz);
-        // y rows outside the fluid (and the wall faces of v) take no part
-        const bool row_ok = a != 1 || (node >= (o ? 0 : 1) && node <= G.ny - 1);
-        const int loc = node - t0[a];
-        li[a][o][t] = loc;
-        if (row_ok && loc >= 0 && loc < tlen[a]) m |= 1u << t;
-      }
-      msk[a][o] = m;
-    }
+    for (int o = 0; o < 2; ++o) b[a][o] = d[a] + stencil_axis<T>(fo[a][o], mhi[a], mlo[a], w[a][o]) - 1;
+  constexpr unsigned lim[3] = {TX + 1, TY + 1, TZ + 1};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const int ox = c == 0 ? 0 : 1, oy = c == 1 ? 0 : 1, oz = c == 2 ? 0 : 1;
-    const unsigned mx = msk[0][ox], my = msk[1][oy], mz = msk[2][oz];
-    if (!(mx && my && mz)) continue;
-    // per node one multiply by the row's value val * wz * wy (in the field
-    // precision, or double for double accumulators)
+    const int ox = stag(c, 0), oy = stag(c, 1), oz = stag(c, 2);
+    const int bx = b[0][ox], by = b[1][oy], bz = b[2][oz];
+    // nodes b .. b + 2 (guard-banded index) meet the tile's b in [0, T + 1]
+    if (!((unsigned)bx <= lim[0] && (unsigned)by <= lim[1] && (unsigned)bz <= lim[2])) continue;
+    A_t *A = acc + c * NODES_P + (bz * PY + by) * PX + bx;
     using W_t = typename std::conditional<std::is_integral<A_t>::value, T, A_t>::type;
     const W_t val = (W_t)(v[c] * scale);
-    const W_t wx[3] = {(W_t)w[0][ox][0], (W_t)w[0][ox][1], (W_t)w[0][ox][2]};
-    A_t *A = acc + c * NODES_P;
+    const T *wx = w[0][ox], *wy = w[1][oy], *wz = w[2][oz];
+#pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
-      if (!(mz >> kk & 1u)) continue;
-      const W_t vz = val * (W_t)w[2][oz][kk];
+      const W_t vz = val * (W_t)wz[kk];
+#pragma unroll
       for (int jj = 0; jj < 3; ++jj) {
-        if (!(my >> jj & 1u)) continue;
-        const W_t vzy = vz * (W_t)w[1][oy][jj];
-        A_t *rowp = A + (li[2][oz][kk] * TY + li[1][oy][jj]) * PX;
+        const W_t vzy = vz * (W_t)wy[jj];
+#pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
-          if (!(mx >> ii & 1u)) continue;
           if constexpr (std::is_integral<A_t>::value)
-            atomicAdd(rowp + li[0][ox][ii], (A_t)__float2int_rn(vzy * wx[ii]));
+            atomicAdd(A + (kk * PY + jj) * PX + ii, (A_t)__float2int_rn(vzy * (W_t)wx[ii]));
           else
-            atomicAdd(rowp + li[0][ox][ii], vzy * wx[ii]);
+            atomicAdd(A + (kk * PY + jj) * PX + ii, vzy * (W_t)wx[ii]);
         }
       }
     }
@@ -757,13 +753,13 @@ __device__ inline void tile_unit(double bound, double dvh, double &unit, bool &p
   scale = (T)(dvh / unit);
 }
 
-// Write-back of a tile: each node with a non-zero accumulator is added to the
-// field once (plain read-modify-write; the tile owns its nodes), by x-rows:
-// TX lanes per row, rows (component, z, y).  A poisoned tile makes every node
-// NaN and raises the status flag.
+// Write-back of a tile: each owned node with a non-zero accumulator is added
+// to the field once (plain read-modify-write; the tile owns its nodes), by
+// x-rows: TX lanes per row, rows (component, z, y).  The wall faces of v
+// (rows j = 0 and j = ny) take no part: they are skipped, or stored as zero
+// when the pass overwrites.  A poisoned tile makes every node NaN and raises
+// the status flag.
 // Rows of f a lane reads before writing them back (loads in flight at once).
-// At C3 in single precision (12 rows per lane): one row at a time 24.1 ms per
-// spreading pass, 2: 24.3, 4: 22.9, 6: 22.8, all 12: 22.5 ms.
 #ifndef PRS_FLUSH_BATCH
 #define PRS_FLUSH_BATCH 12
 #endif
@@ -771,27 +767,31 @@ __device__ inline void tile_unit(double bound, double dvh, double &unit, bool &p
 // acc == nullptr: a tile with nothing to add (only written when overwriting).
 // overwrite: every node of the tile is stored (zero where acc is), f is not
 // read; otherwise only nonzero sums are added.
-template <typename T, typename A_t, int TX, int TY, int TZ, int PX>
+template <typename T, typename A_t, int TX, int TY, int TZ>
 __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0, int k0,
                                   double unit, bool poison, bool overwrite, T *f0, T *f1, T *f2,
                                   uint32_t *status) {
   constexpr bool kFixed = std::is_integral<A_t>::value;
+  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
   static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
   constexpr int kRows = 3 * TZ * TY, kStep = kTileThreads / TX;
   constexpr int kPer = (kRows + kStep - 1) / kStep;   // rows per lane
   const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
   // the lane's q-th row: its node's field, index and sum; false where the
   // row has nothing to write
-  auto node = [&](int q, T *&Fp, size_t &g, A_t &a) {
+  auto node = [&](int q, T *&Fp, size_t &g, A_t &a, bool &wall) {
     const int row = threadIdx.x / TX + q * kStep;
     if (row >= kRows || i >= G.nx) return false;
-    a = acc ? acc[row * PX + lx] : (A_t)0;
-    if (a == (A_t)0 && !poison && !overwrite) return false;
     const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
     const int lz = rz / TY, ly = rz - lz * TY;
     const int j = j0 + ly, k = k0 + lz;
     const int nyc = G.ny + (c == 1 ? 1 : 0);
     if (j >= nyc || k >= G.nz) return false;
+    wall = c == 1 && (j == 0 || j == G.ny);
+    a = (acc && !wall) ? acc[c * (PX * PY * PZ) + ((lz + kGuard) * PY + ly + kGuard) * PX + lx +
+                             kGuard]
+                       : (A_t)0;
+    if (wall ? !overwrite : (a == (A_t)0 && !poison && !overwrite)) return false;
     g = ((size_t)k * nyc + j) * G.nx + i;
     Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
     return true;
@@ -808,15 +808,21 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
       T *Fp;
       size_t g;
       A_t a;
+      bool wall;
       old[b] = (T)0;
-      if (!overwrite && q0 + b < kPer && node(q0 + b, Fp, g, a)) old[b] = Fp[g];
+      if (!overwrite && q0 + b < kPer && node(q0 + b, Fp, g, a, wall)) old[b] = Fp[g];
     }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       T *Fp;
       size_t g;
       A_t a;
-      if (q0 + b >= kPer || !node(q0 + b, Fp, g, a)) continue;
+      bool wall;
+      if (q0 + b >= kPer || !node(q0 + b, Fp, g, a, wall)) continue;
+      if (wall) {
+        Fp[g] = (T)0;
+        continue;
+      }
       const T v = poison ? (T)NAN : (kFixed ? (T)((double)a * unit) : (T)a);
       Fp[g] = old[b] + v;
     }
@@ -827,28 +833,30 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
 // SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
 //        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
 //        sorted order read at perm[k].
-// Waves per SIMD the spreading kernel is compiled for: three 512-thread
-// tiles per compute unit in single precision (at most 80 VGPRs; one more
-// register drops the kernel to two tiles per CU and costs about 30 %).
+// Waves per SIMD the spreading kernel is compiled for: two 512-thread tiles
+// per compute unit in single precision (the guard-banded accumulators take
+// 57.6 KB of LDS), one in double precision.
 template <typename T>
 struct TileWaves {
-  static constexpr int value = sizeof(T) == 4 ? 3 * kTileThreads / 256 : 1;
+  static constexpr int value = sizeof(T) == 4 ? 2 * kTileThreads / 256 : kTileThreads / 256;
 };
 
 template <typename T, int SRC>
 __global__ __launch_bounds__(kTileThreads)
 __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
-    const double *__restrict__ templ, const T *__restrict__ src, const int *__restrict__ perm,
-    const float *__restrict__ vmax, T *f0, T *f1, T *f2, uint32_t *status, TileCache tc) {
+    const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ src,
+    const int *__restrict__ perm, const float *__restrict__ vmax, T *f0, T *f1, T *f2,
+    uint32_t *status, TileCache tc) {
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
-  constexpr int PX = TX + PRS_SPREAD_PAD, NODES_P = PX * TY * TZ;
+  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
+  constexpr int NODES_P = PX * PY * PZ;
   using A_t = typename TileAcc<T>::type;
   __shared__ A_t acc[3 * NODES_P];
   __shared__ int c_idx[kTileCand];
   __shared__ int c_l0[kTileCand];
   __shared__ int c_pref[kTileCand + 1];
-  __shared__ double c_x[kTileCand][3];
+  __shared__ TileCand<T> c_geo[kTileCand];
   __shared__ int c_n;
   __shared__ unsigned c_list[kTileList];   // culled (candidate << 10 | marker)
   __shared__ int c_list_n;
@@ -871,11 +879,12 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   const double ctr[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
   const double hw[3] = {0.5 * (hi[0] - lo[0]) + 1e-9, 0.5 * (hi[1] - lo[1]) + 1e-9,
                         0.5 * (hi[2] - lo[2]) + 1e-9};
-  // the same box for the markers themselves (no sphere radius)
+  // the same box for the markers themselves (no sphere radius), widened by
+  // 1e-6 h for the single-precision stencil positions
   const double mctr[3] = {(i0 + 0.5 * (TX - 0.5)) * h, (j0 + 0.5 * (TY - 0.5)) * h,
                           (k0 + 0.5 * (TZ - 0.5)) * h};
-  const double mhw[3] = {(0.5 * TX + 1.25) * h + 1e-9 * h, (0.5 * TY + 1.25) * h + 1e-9 * h,
-                         (0.5 * TZ + 1.25) * h + 1e-9 * h};
+  const double mhw[3] = {(0.5 * TX + 1.25 + 1e-6) * h, (0.5 * TY + 1.25 + 1e-6) * h,
+                         (0.5 * TZ + 1.25 + 1e-6) * h};
 
   constexpr bool kFixed = std::is_integral<A_t>::value;
   const double dvh = G.dV * G.inv_h * G.inv_h * G.inv_h;
@@ -892,8 +901,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   if (cached >= 0) {
     if (cached == 0) {
       if (tc.overwrite)
-        tile_flush<T, A_t, TX, TY, TZ, PX>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
-                                           status);
+        tile_flush<T, A_t, TX, TY, TZ>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
+                                       status);
       return;
     }
     const unsigned *reg = tc.items + (size_t)tile * tc.cap;
@@ -901,9 +910,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
       const int k = (int)reg[t];
       c_idx[t] = k;
-      c_x[t][0] = xs[k];
-      c_x[t][1] = xs[N + k];
-      c_x[t][2] = xs[2 * N + k];
+      tile_cand<T, TX, TY, TZ>(G, xs[k], xs[N + k], xs[2 * N + k], i0, j0, k0, c_geo[t].d,
+                               c_geo[t].fo);
     }
     if (kFixed) {
       __shared__ double r_wv[kTileThreads / 64];
@@ -921,14 +929,12 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     for (int it = threadIdx.x; it < cached; it += blockDim.x) {
       const unsigned cd = itm[it];
       const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
-      const int k = c_idx[sc];
-      const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
-                           c_x[sc][2] + R * templ[3 * l + 2]};
-      spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
+      spread_visit<T, SRC, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, src, perm, c_idx[sc], l,
+                                       M, scale, acc);
     }
     __syncthreads();
-    tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1,
-                                       f2, status);
+    tile_flush<T, A_t, TX, TY, TZ>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
+                                   status);
     return;
   }
 
@@ -960,9 +966,7 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
         const int slot = atomicAdd(&c_n, 1);
         if (slot < kTileCand) {
           c_idx[slot] = k;
-          c_x[slot][0] = px;
-          c_x[slot][1] = py;
-          c_x[slot][2] = pz;
+          tile_cand<T, TX, TY, TZ>(G, px, py, pz, i0, j0, k0, c_geo[slot].d, c_geo[slot].fo);
         }
       }
     }
@@ -973,8 +977,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   if (nc == 0) {
     if (record && threadIdx.x == 0) tc.count[tile] = 0;
     if (tc.overwrite)
-      tile_flush<T, A_t, TX, TY, TZ, PX>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
-                                         status);
+      tile_flush<T, A_t, TX, TY, TZ>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
+                                     status);
     return;
   }
   if (nc > kTileCand) {
@@ -1001,10 +1005,12 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   for (int s = threadIdx.x; s < kTileCand; s += blockDim.x) {
     int cnt = 0, l0 = 0;
     if (s < nc) {
-      double thi = (yhi - c_x[s][1]) / R, tlo = (ylo - c_x[s][1]) / R;
-      const double dx = fmax(fabs(min_image(c_x[s][0] - mctr[0], G.Lx)) - mhw[0], 0.0);
-      const double dz = fmax(fabs(min_image(c_x[s][2] - mctr[2], G.Lz)) - mhw[2], 0.0);
-      const double tmax = sqrt(fmax(1.0 - (dx * dx + dz * dz) / (R * R), 0.0)) + 1e-9;
+      const int k = c_idx[s];
+      const double cx = xs[k], cy = xs[N + k], cz = xs[2 * N + k];
+      double thi = (yhi - cy) / R, tlo = (ylo - cy) / R;
+      const double dx = fmax(fabs(min_image(cx - mctr[0], G.Lx)) - mhw[0], 0.0);
+      const double dz = fmax(fabs(min_image(cz - mctr[2], G.Lz)) - mhw[2], 0.0);
+      const double tmax = sqrt(fmax(1.0 - (dx * dx + dz * dz) / (R * R), 0.0)) + 1e-6;
       thi = fmin(thi, tmax);
       tlo = fmax(tlo, -tmax);
       l0 = max((int)floor((nl * (1.0 - thi) - 1.0) * 0.5) - 1, 0);
@@ -1065,10 +1071,11 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
         if (c_pref[mid] <= item) a = mid; else b = mid;
       }
       const int l = c_l0[a] + (item - c_pref[a]);
-      const double X0 = c_x[a][0] + R * templ[3 * l], X1 = c_x[a][1] + R * templ[3 * l + 1],
-                   X2 = c_x[a][2] + R * templ[3 * l + 2];
+      const int k = c_idx[a];
+      const double X0 = xs[k] + R * templ[3 * l], X1 = xs[N + k] + R * templ[3 * l + 1],
+                   X2 = xs[2 * N + k] + R * templ[3 * l + 2];
       // a marker outside the tile's reach box touches none of its nodes
-      // (conservative; the exact test is the stencil mask)
+      // (conservative; the exact test is each component's stencil range)
       pass = fabs(min_image(X0 - mctr[0], G.Lx)) <= mhw[0] && fabs(X1 - mctr[1]) <= mhw[1] &&
              fabs(min_image(X2 - mctr[2], G.Lz)) <= mhw[2];
       code = ((unsigned)a << 10) | (unsigned)l;
@@ -1088,11 +1095,9 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
       for (int it = threadIdx.x; it < listed; it += blockDim.x) {
         const unsigned cd = c_list[it];
         const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
-        const int k = c_idx[sc];
         if (keep) reg[rbase + it] = cd;
-        const double X[3] = {c_x[sc][0] + R * templ[3 * l], c_x[sc][1] + R * templ[3 * l + 1],
-                             c_x[sc][2] + R * templ[3 * l + 2]};
-        spread_marker<T, SRC, TX, TY, TZ, PX>(G, X, src, perm, k, l, M, scale, i0, j0, k0, acc);
+        spread_visit<T, SRC, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, src, perm, c_idx[sc],
+                                         l, M, scale, acc);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1107,8 +1112,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     tc.ncand[tile] = nc;
   }
   __syncthreads();
-  tile_flush<T, A_t, TX, TY, TZ, PX>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
-                                     status);
+  tile_flush<T, A_t, TX, TY, TZ>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
+                                 status);
 }
 
 
@@ -1154,18 +1159,19 @@ hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, con
   if (n == 0) return hipSuccess;
   const int ntiles = spread_tile_count<T>(G);
   if (!tc.items) tc.mode = 0;
+  const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
   // caller values: their per-sphere maxima first (the correction buffer's are
   // written by the interpolation pass that fills it)
   if (src_caller) {
     hipError_t e = launch_sphere_vmax<T>(s, G, S, n, src_caller);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_spread_tiles<T, 1>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
-                       G, C, S.start, S.xs[0], n, S.templ, src_caller, S.perm, S.vmax, f[0],
+                       G, C, S.start, S.xs[0], n, S.templ, tm, src_caller, S.perm, S.vmax, f[0],
                        f[1], f[2], S.status, tc);
   } else {
     hipLaunchKernelGGL((k_spread_tiles<T, 0>), dim3(xcd_grid(ntiles)), dim3(kTileThreads), 0, s,
-                       G, C, S.start, S.xs[0], n, S.templ, (const T *)S.dF, S.perm, S.vmax, f[0],
-                       f[1], f[2], S.status, tc);
+                       G, C, S.start, S.xs[0], n, S.templ, tm, (const T *)S.dF, S.perm, S.vmax,
+                       f[0], f[1], f[2], S.status, tc);
   }
   return hipGetLastError();
 }
@@ -1176,6 +1182,11 @@ int spread_tile_count(const Geom &G) {
   return ((G.nx + TX - 1) / TX) * ((G.ny + 1 + TY - 1) / TY) * ((G.nz + TZ - 1) / TZ);
 }
 template int spread_tile_count<float>(const Geom &);
+
+int spread_tile_dim(int esz, int axis) {
+  if (esz == 4) return axis == 0 ? TileShape<float>::X : (axis == 1 ? TileShape<float>::Y : TileShape<float>::Z);
+  return axis == 0 ? TileShape<double>::X : (axis == 1 ? TileShape<double>::Y : TileShape<double>::Z);
+}
 template int spread_tile_count<double>(const Geom &);
 
 template hipError_t launch_spread_tiles<float>(hipStream_t, const Geom &, const Cells &,

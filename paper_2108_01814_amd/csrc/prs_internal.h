@@ -51,7 +51,9 @@ struct Cells {
 struct Mech {
   double m, I;
   double fg[3];           // buoyant weight (rho_p - rho_f) V g
-  double kn, dn_pp, dn_pw, kt, dt_pp, dt_pw, mu;
+  // normal and tangential stiffness and damping, sphere-sphere (pp) and
+  // sphere-wall (pw)
+  double kn_pp, kn_pw, dn_pp, dn_pw, kt_pp, kt_pw, dt_pp, dt_pw, mu;
   double dtp;             // particle substep
   double skin_half2;      // (skin/2)^2
 };
@@ -80,6 +82,7 @@ struct Scratch {
   int tc_cap;
   double *slip_hist;          // [kMaxSlip + 1 + 256]: per pass, zero-forcing, block partials
   int *ncand, *cand;          // [n], [kCandCap][n]
+  int *bed;                   // [n]: bed marks of the bed / flying detection (sorted order)
   // contact history, internal SoA layout [slot][n], double-buffered
   int *h_cnt[2], *h_id[2];
   double *h_dt[2], *h_uin[2];
@@ -93,6 +96,10 @@ struct Scratch {
   uint32_t *status;
   unsigned long long *counters;   // [0] directed contacts, [1] pp last, [2] wall last
   double *templ;                  // [nl][3]
+  // marker offsets (R / h) t_l in node units: [nl][8] floats (rounded value
+  // xyz, pad, remainder xyz, pad) and [nl][4] doubles (xyz, pad)
+  float *tm32;
+  double *tm64;
   int *lane_order;                // [nl]: marker handled by interpolation lane i
 };
 
@@ -104,6 +111,7 @@ struct LearnArgs {
   const float *norm;           // feature mean/std, target mean/std
   float *feat;                 // feature pass: [n][nl][16] in caller order
   const int *perm;             // sorted position -> caller index
+  const float *gelu_tab;       // GELU table of the fused pass (float4 [kGeluTabN])
 };
 
 // Per-tile record of the spreading's candidate spheres and culled markers,
@@ -125,7 +133,8 @@ struct TileCache {
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_template(hipStream_t s, double *t, int *lane_order, int nl);
+hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, int *lane_order,
+                           int nl, double r_over_h);
 
 hipError_t launch_sort(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
                        const double *x_caller, int n, int nkeys_scan_levels);
@@ -175,6 +184,8 @@ void mlp_buffers(const prs_mlp *mlp, LearnArgs *la);
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
                                T *f[3], int n, const T *src_caller, TileCache tc = TileCache{});
+// Nodes per axis of a spreading tile for fields of esz-byte elements.
+int spread_tile_dim(int esz, int axis);
 // Tiles of the spreading grid for fields of type T.
 template <typename T>
 int spread_tile_count(const Geom &G);
@@ -197,5 +208,16 @@ hipError_t launch_substep(hipStream_t s, const Scratch &S, const Geom &G, const 
 hipError_t launch_contact_list(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
                                int n, int32_t *pairs, long long cap, int phase);
 hipError_t launch_reset_status(hipStream_t s, const Scratch &S);
+template <typename T>
+hipError_t launch_inner_fluid(hipStream_t s, const Geom &G, const Scratch &S, const T *u[3],
+                              const double *x, int n, double *inner);
+template <typename T>
+hipError_t launch_inner_step(hipStream_t s, const Geom &G, const Scratch &S, const T *uh[3],
+                             const T *f[3], double adt, double rho_f, int n, const double *prev,
+                             double *inner_out);
+hipError_t launch_bed_seed(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G, int n);
+hipError_t launch_bed_pass(hipStream_t s, const Scratch &S, int n, unsigned long long *changed);
+hipError_t launch_bed_out(hipStream_t s, const Scratch &S, int n, int8_t *flags,
+                          unsigned long long *count);
 
 }  // namespace prs

@@ -199,6 +199,19 @@ __global__ void k_mlp_adam(float *master, float *m, float *v, const float *__res
   wbf[i] = to_bf16(w);
 }
 
+// Table of the GELU of the fused learned pass (gelu_tab): piece i on
+// [z_i, z_i + h], z_i = -6 + i h, h = 1/64, the quadratic through Phi at its
+// ends and midpoint, Phi(z) = erfc(-z / sqrt 2) / 2 in double precision.
+__global__ void k_gelu_table(float4 *tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kGeluTabN) return;
+  const double h = 1.0 / (double)kGeluInvStep, z = (double)kGeluZ0 + i * h;
+  auto Phi = [](double v) { return 0.5 * erfc(-v * 0.70710678118654752440); };
+  const double p0 = Phi(z), pm = Phi(z + 0.5 * h), p1 = Phi(z + h);
+  const double c2 = 2.0 * (p0 + p1 - 2.0 * pm), c1 = p1 - p0 - c2;
+  tab[i] = make_float4((float)p0, (float)c1, (float)c2, 0.f);
+}
+
 __global__ void k_mlp_round(const float *__restrict__ master, unsigned short *wbf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kMlpParams) wbf[i] = to_bf16(master[i]);
@@ -350,6 +363,7 @@ using namespace prs;
 struct prs_mlp {
   float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *partial = nullptr;
   float *loss_part = nullptr, *norm = nullptr;
+  float4 *gelu_tab = nullptr;
   double *loss = nullptr;
   unsigned short *wbf = nullptr;
   int t = 0;
@@ -361,6 +375,7 @@ void prs::mlp_buffers(const prs_mlp *mlp, prs::LearnArgs *la) {
   la->wbf = mlp->wbf;
   la->master = mlp->master;
   la->norm = mlp->norm;
+  la->gelu_tab = reinterpret_cast<const float *>(mlp->gelu_tab);
 }
 
 namespace {
@@ -471,13 +486,16 @@ int prs_mlp_create(const float *params, const float *norm, prs_mlp **out) {
             hipMalloc(&m->loss_part, (size_t)m->max_waves * 4) == hipSuccess &&
             hipMalloc(&m->norm, kMlpNorm * 4) == hipSuccess &&
             hipMalloc(&m->loss, sizeof(double)) == hipSuccess &&
-            hipMalloc(&m->wbf, P * 2) == hipSuccess;
+            hipMalloc(&m->wbf, P * 2) == hipSuccess &&
+            hipMalloc(&m->gelu_tab, kGeluTabN * sizeof(float4)) == hipSuccess;
   ok = ok && hipMemcpy(m->master, params, P * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(m->norm, norm, kMlpNorm * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemset(m->m, 0, P * 4) == hipSuccess && hipMemset(m->v, 0, P * 4) == hipSuccess;
   if (ok) {
     hipLaunchKernelGGL(k_mlp_round, dim3((kMlpParams + 255) / 256), dim3(256), 0, nullptr,
                        m->master, m->wbf);
+    hipLaunchKernelGGL(k_gelu_table, dim3((kGeluTabN + 255) / 256), dim3(256), 0, nullptr,
+                       m->gelu_tab);
     ok = hipDeviceSynchronize() == hipSuccess;
   }
   if (!ok) {
@@ -491,7 +509,7 @@ int prs_mlp_create(const float *params, const float *norm, prs_mlp **out) {
 void prs_mlp_destroy(prs_mlp *m) {
   if (!m) return;
   void *ptrs[] = {m->master, m->m, m->v, m->grad, m->partial, m->loss_part, m->norm, m->loss,
-                  m->wbf};
+                  m->wbf, m->gelu_tab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;

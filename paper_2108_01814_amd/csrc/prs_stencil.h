@@ -6,43 +6,84 @@
 
 namespace prs {
 
-// Three-point kernel weights of the nodes ic-1, ic, ic+1 for the offset
-// r0 = s - ic in [-1/2, 1/2) (s in node units): with q = sqrt(1 - 3 r0^2),
-// w(ic) = (1+q)/3 and w(ic+-1) = (2 +- 3 r0 - q)/6.  Interpolation and
-// spreading use this one function, so they are exact adjoints.
+// ---- stencil geometry shared by the interpolation and the spreading ------
+// Both operations evaluate a marker's delta-kernel weights with the same
+// arithmetic from the same inputs, so they are exact adjoints:
+//   - the sphere centre in node units, s = x / h, is split once per sphere
+//     into an integer node I = floor(s) and a fraction phi = s - I in [0, 1)
+//     (double precision), and fo = phi - o for the two staggering offsets
+//     o = 0 (the component along the axis) and o = 1/2 (the other two),
+//     rounded to the grid precision;
+//   - the marker offset (R / h) t_l in node units is a per-template value
+//     (m_hi + m_lo in single precision: m_hi = the offset rounded, m_lo its
+//     remainder; m_lo = 0 in double precision);
+//   - the stencil centre c = floor(fo + m_hi + 1/2) and the offset of the
+//     marker from it, r = ((m_hi - c) + fo) + m_lo, which is within a few
+//     rounding errors of the exact offset even though |fo + m| reaches R/h
+//     (m_hi - c is exact or nearly so, and |r| <= 1/2);
+//   - the three-point kernel (regularised delta function) at the nodes
+//     I + c - 1, I + c, I + c + 1: with q = sqrt(1 - 3 r^2),
+//     w(c) = (1 + q) / 3, w(c -+ 1) = (2 -+ 3 r - q) / 6.
+// Near r = +-1/2 the floor may pick either neighbour; both choices give the
+// same weights on the same nodes (w = 0, 1/2, 1/2 and 1/2, 1/2, 0), so the
+// stencil is continuous there.
+
+// Integer node and staggered fractions of one coordinate of a sphere centre.
 template <typename T>
-__device__ inline void kernel3(double s, int &ic, T w[3]) {
-  const double c = floor(s + 0.5);
-  ic = (int)c;
-  const T r = (T)(s - c);
-  const T q = sqrt((T)1 - (T)3 * r * r);
-  w[0] = ((T)2 - (T)3 * r - q) * (T)(1.0 / 6.0);
-  w[1] = ((T)1 + q) * (T)(1.0 / 3.0);
-  w[2] = ((T)2 + (T)3 * r - q) * (T)(1.0 / 6.0);
+__device__ inline void sphere_axis(double x, double inv_h, int &I, T fo[2]) {
+  const double s = x * inv_h;
+  const double fl = floor(s);
+  I = (int)fl;
+  const T phi = (T)(s - fl);
+  fo[0] = phi;
+  fo[1] = phi - (T)0.5;
 }
 
-// Staggering of component c in units of h: u on x-faces, v on y-faces, w on
-// z-faces.
-__device__ inline double stagger(int c, int axis) { return c == axis ? 0.0 : 0.5; }
-
-// Stencil of one marker for one component: centre node per axis (unwrapped)
-// and the three weights per axis.
+// Stencil along one axis: centre offset c (nodes I + c - 1 .. I + c + 1)
+// and the three weights.  Written with explicit fused operations so that
+// every inlined copy rounds identically.
 template <typename T>
-struct Stencil {
-  int ic[3];
-  T w[3][3];
+__device__ inline int stencil_axis(T fo, T mhi, T mlo, T w[3]) {
+  const T cf = floor((fo + mhi) + (T)0.5);
+  const T r = ((mhi - cf) + fo) + mlo;
+  const T q = sqrt(fma((T)-3 * r, r, (T)1));
+  const T a = (T)2 - q;
+  w[0] = fma((T)-3, r, a) * (T)(1.0 / 6.0);
+  w[1] = fma(q, (T)(1.0 / 3.0), (T)(1.0 / 3.0));
+  w[2] = fma((T)3, r, a) * (T)(1.0 / 6.0);
+  return (int)cf;
+}
+
+// Staggering index of component c along axis a: 0 for the component along
+// the axis (nodes on cell faces), 1 for the others (cell centres).
+__device__ inline constexpr int stag(int c, int a) { return c == a ? 0 : 1; }
+
+// Per-template marker offsets in node units, float4 pairs (hi xyz, lo xyz)
+// in single precision or one double4 (xyz) in double precision.
+template <typename T>
+struct MarkerOffset;
+template <>
+struct MarkerOffset<float> {
+  __device__ static inline void load(const float *tm, int l, float hi[3], float lo[3]) {
+    const float4 a = reinterpret_cast<const float4 *>(tm)[2 * l];
+    const float4 b = reinterpret_cast<const float4 *>(tm)[2 * l + 1];
+    hi[0] = a.x; hi[1] = a.y; hi[2] = a.z;
+    lo[0] = b.x; lo[1] = b.y; lo[2] = b.z;
+  }
+};
+template <>
+struct MarkerOffset<double> {
+  __device__ static inline void load(const double *tm, int l, double hi[3], double lo[3]) {
+    const double *p = tm + 4 * l;
+    hi[0] = p[0]; hi[1] = p[1]; hi[2] = p[2];
+    lo[0] = lo[1] = lo[2] = 0.0;
+  }
 };
 
-template <typename T>
-__device__ inline void make_stencil(const Geom &G, int c, const double X[3], Stencil<T> &S) {
-  for (int a = 0; a < 3; ++a) kernel3<T>(X[a] * G.inv_h - stagger(c, a), S.ic[a], S.w[a]);
-}
-
-// First node row of the brick of a sphere of centre xc for component c along
-// one axis: the lowest stencil node any marker of the sphere can reach.
-__device__ inline int brick_lo(double xc, double R, double inv_h, double o) {
-  return (int)floor((xc - R) * inv_h - o + 0.5) - 1;
-}
+// Brick of one sphere in the interpolation: nodes I - E .. I - E + nb - 1 per
+// axis, with E = ceil(R/h) + 1 and nb = 2 ceil(R/h) + 4, which holds every
+// node of every marker's stencil (|m| < R/h, fo in [-1/2, 1)).
+__host__ __device__ inline int brick_reach(double R, double h) { return (int)ceil(R / h - 1e-9) + 1; }
 
 // ---- per-sphere block reductions -----------------------------------------
 // Eight columns per lane: the force and torque terms (0..5) and two slip

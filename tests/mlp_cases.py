@@ -4,8 +4,10 @@ parity tests (seeded construction only; no arithmetic of the method).
 `dyadic_network` builds a 16-64-64-16 network and a batch on which every
 value the network rounds to BF16 is computed exactly in single precision on
 any accumulation order: inputs and weights are small dyadic rationals, and
-the biases put every hidden pre-activation at |z| >= 6, where GELU(z) equals
-z (z > 0) or is below 1e-8 (z < 0) in single precision.  Targets are placed
+the biases put every hidden pre-activation at z >= 6, where GELU(z) and its
+derivative equal z and 1 in single precision (every unit is active: an
+inactive unit's gradient would be a GELU tail of 1e-10, which Adam's
+normalisation by |g| + eps magnifies).  Targets are placed
 at y - 3 d with d a multiple of 1/8, so the output error 2 (y - T) / (3 B) is
 again exact for a power-of-two batch B.  BF16 rounding decisions therefore
 cannot differ between an FP32 device and the FP64 oracle."""
@@ -26,14 +28,12 @@ def dyadic_network(seed: int, B: int = 4096):
     """(params float64 [6288], X float64 [B, 16]); targets come from
     dyadic_targets once the network output is known."""
     rng = np.random.default_rng(seed)
-    on1 = rng.random(N_HID) < 0.5
-    on2 = rng.random(N_HID) < 0.5
     d = {}
     d["W1"] = np.zeros((N_HID, N_IN))
     d["W1"][:, :N_FEAT] = rng.integers(-1, 2, size=(N_HID, N_FEAT)) / 16.0
-    d["b1"] = np.where(on1, 8.0, -8.0)
+    d["b1"] = np.full(N_HID, 8.0)
     d["W2"] = rng.integers(-1, 2, size=(N_HID, N_HID)) / 128.0
-    d["b2"] = np.where(on2, 12.0, -12.0)
+    d["b2"] = np.full(N_HID, 12.0)
     d["W3"] = np.zeros((N_OUT, N_HID))
     d["W3"][:3] = rng.integers(-4, 5, size=(3, N_HID)) / 64.0
     d["b3"] = np.zeros(N_OUT)

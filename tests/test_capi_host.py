@@ -39,6 +39,8 @@ def test_params_struct_matches_header_size():
     assert (p.nx, p.ny, p.nz) == (8, 9, 10)
     assert P.Params.h.offset == 16 and P.Params.radius.offset == 24
     assert P.Params.max_particles.offset > P.Params.precision.offset
+    assert P.Params.contact_model.offset > P.Params.max_particles.offset
+    assert P.Params.e_t.offset == P.Params.t_c.offset + 8
 
 
 @pytest.mark.parametrize("bad", [
@@ -46,6 +48,8 @@ def test_params_struct_matches_header_size():
     dict(e_n=0.0), dict(e_n=1.5), dict(kt_ratio=0.0), dict(precision=3), dict(max_iter=64),
     dict(tol_mode=2), dict(skin=-0.1), dict(nx=2),   # periodic box shorter than three cells
     dict(mu=-1.0), dict(dt_f=0.0), dict(gravity=(0.0, float("nan"), 0.0)),
+    dict(contact_model=2), dict(contact_model=1, t_c=0.0), dict(contact_model=1, e_t=0.0),
+    dict(contact_model=1, e_t=1.5), dict(nx=30),    # too narrow for a spreading tile's image
 ])
 def test_create_rejects_bad_parameters(bad):
     kw = dict(nx=80, ny=100, nz=80, max_particles=10)

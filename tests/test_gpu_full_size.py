@@ -1,6 +1,7 @@
-"""Parity at the full size of the benchmark: the 1,048,576-sphere C3 bed with
-FP32 fields, in the launch configuration bench.py times (3 forcing
-iterations, 20 substeps, skin 0.1).
+"""Parity at full size: the 1,048,576-sphere C3 bed with FP32 fields, in the
+launch configuration bench.py times (3 forcing iterations, 20 substeps, skin
+0.1), and the 22,000-sphere C2 bed (D/h = 16, 804 markers) in both
+precisions (FP64 fields 1e-11, FP32 fields 1e-5).
 
 The oracle cannot run the whole bed, so it runs a 12D x Ly x 12D column of
 it (the spheres with centres in the column, the same FP32 field on the
@@ -56,22 +57,27 @@ def orc():
     return oracle
 
 
-@pytest.fixture(scope="module")
-def c3(P):
-    """The C3 bed, its FP32 field, and the GPU step on the whole bed."""
+CASES = {"c3-f32": (W.C3, 0), "c2-f32": (W.C2, 0), "c2-f64": (W.C2, 1)}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def full(P, request):
+    """A bed, its field in the case's precision, and the GPU step on the
+    whole bed."""
     import torch
 
     from paper_2108_01814_amd import learned as L
 
-    w = W.C3
+    w, precision = CASES[request.param]
+    dt = torch.float32 if precision == 0 else torch.float64
     bed = W.make_bed(w)
     modes = W.flow_modes(w, bed.bed_top)
-    g = W.fluid_field(w, modes, device="cuda", dtype=torch.float32)
+    g = W.fluid_field(w, modes, device="cuda", dtype=dt)
     x = torch.as_tensor(bed.x, device="cuda")
     u = torch.as_tensor(bed.u, device="cuda")
     om = torch.as_tensor(bed.om, device="cuda")
-    print(f"C3 step on {w.n} spheres, grid {w.grid}", flush=True)
-    with P.Context(L.params_for(w, P.F32, w.n, skin=0.1)) as ctx:
+    print(f"{w.name} step on {w.n} spheres, grid {w.grid}, precision {precision}", flush=True)
+    with P.Context(L.params_for(w, precision, w.n, skin=0.1)) as ctx:
         H = P.History.zeros(w.n)
         f = [torch.zeros_like(a) for a in g]
         Fh, Th, st = ctx.step(g, f, x, u, om, H, zero_f=True)
@@ -80,7 +86,9 @@ def c3(P):
                    count=H.count.cpu().numpy().astype(np.int32), st=st)
         out["f_window"] = window_field(w, f, *column(w)[2:])
         del f
-    return w, bed, g, out
+    yield w, bed, g, out, precision
+    del g
+    torch.cuda.empty_cache()
 
 
 def window_field(w, g, wi0, wnx, wk0, wnz):
@@ -95,8 +103,8 @@ def window_field(w, g, wi0, wnx, wk0, wnz):
             for a in g]
 
 
-def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
-    w, bed, g, gpu = c3
+def test_step_matches_oracle_inside_a_column(P, orc, full):
+    w, bed, g, gpu, precision = full
     assert gpu["st"]["iterations"] == w.n_iter and gpu["st"]["flags"] == 0
     ph = W.PHYS
     nx, ny, nz = w.grid
@@ -121,8 +129,8 @@ def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
             (bed.x[win, 2] >= z0 + CORE_MARGIN) & (bed.x[win, 2] < z0 + WIDTH - CORE_MARGIN))
     assert core.sum() > 150
     gi = win[core]
-    tol = 1e-5
-    print("C3 column core: %d spheres; errors F_h %.2e T_h %.2e x %.2e u %.2e om %.2e" % (
+    tol = 1e-5 if precision == 0 else 1e-11
+    print(f"{w.name} column core:" + " %d spheres; errors F_h %.2e T_h %.2e x %.2e u %.2e om %.2e" % (
         core.sum(), rel_err(gpu["Fh"][gi], out["Fh"][core]), rel_err(gpu["Th"][gi], out["Th"][core]),
         np.abs(gpu["x"][gi] - xs[core]).max(), rel_err(gpu["u"][gi], us[core]),
         rel_err(gpu["om"][gi], oms[core])), flush=True)
@@ -141,7 +149,7 @@ def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
         a = gpu["f_window"][c][k0:k1, :, i0:i1]
         b = f[c][k0:k1, :, i0:i1]
         assert np.abs(b).max() > 0
-        print(f"C3 column core f[{c}]: error {rel_err(a, b):.2e}", flush=True)
+        print(f"{w.name} column core f[{c}]: error {rel_err(a, b):.2e}", flush=True)
         assert rel_err(a, b) < tol
     # contact histories: the same partners (window indices mapped to the bed's)
     assert np.array_equal(gpu["count"][gi], H.cnt[core])
@@ -150,10 +158,12 @@ def test_c3_step_matches_oracle_inside_a_column(P, orc, c3):
         assert np.array_equal(a[:n], mapped)
 
 
-def test_c3_contact_list_bit_exact(P, orc, c3):
+def test_contact_list_bit_exact(P, orc, full):
     import torch
 
-    w, bed, g, gpu = c3
+    w, bed, g, gpu, precision = full
+    if precision == 1:
+        pytest.skip("the contact list does not depend on the field precision")
     nx, ny, nz = w.grid
     x = np.ascontiguousarray(bed.x)
     with P.Context(P.make_params(nx=nx, ny=ny, nz=nz, h=w.h, radius=0.5 * W.PHYS["D"],

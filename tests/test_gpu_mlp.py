@@ -167,17 +167,24 @@ def test_dyadic_gradient_parity(P, orc):
 
 
 def test_dyadic_adam_parity(P, orc):
+    """Adam's arithmetic on the same gradient: the device's step from its
+    gradient against the oracle's step from that gradient (a gradient entry
+    that cancels to ~1e-8 over the batch differs between FP32 and FP64
+    accumulation by a relative 1e-4, which Adam's g / (|g| + eps) would
+    magnify; the gradient itself is compared above)."""
     net, params, X, T, Y, Xd, Td = dyadic_setup(P, orc)
-    lo, go = orc.mlp_loss_grad(params, X, T)
     ref = params.copy()
     m = np.zeros_like(ref)
     v = np.zeros_like(ref)
     lr = 1e-3
     g, _ = net.grad(Xd, Td)
     net.adam(g, lr=lr)                       # explicit gradient
-    orc.mlp_adam(ref, m, v, go, 1, lr=lr)
+    orc.mlp_adam(ref, m, v, g.cpu().numpy().astype(np.float64), 1, lr=lr)
     got, _ = net.get()
-    assert np.abs(got - ref).max() <= 1e-5 * lr
+    # within 1e-5 of the step, plus the FP32 rounding of the stored weight
+    # (the biases of 8 and 12 have an FP32 spacing near 1e-6)
+    room = 1e-5 * lr + 0.5 * np.spacing(np.abs(params).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(got - ref) <= room)
     # a step from the kept gradient of the latest backward equals the step
     # from that gradient passed explicitly (bitwise), on a second network
     twin = P.Mlp(params.astype(np.float32), np.concatenate(
