@@ -351,6 +351,17 @@ int prs_mlp_standardize(prs_mlp *mlp, void *stream, const float *X, const float 
  * scratch buffer.  Synchronous.  PRS_EINVAL for count < 2 or NULL arrays. */
 int prs_mlp_fit_norm(void *stream, const float *X, const float *T, int64_t count, float *norm);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): prs_mlp_fit_norm
+ * with the same arguments, results and errors, but no allocation of any
+ * kind.  Its scratch (partial sums and statistics, 39,216 bytes) is a static
+ * device array of the library, one instance per device, held until the
+ * process ends; its size does not depend on count, so every count >= 2 is
+ * accepted.  Calls that overlap on one device share that array and race:
+ * issue them one at a time per device.  Synchronous. */
+int prs_mlp_fit_norm_noalloc(void *stream, const float *X, const float *T, int64_t count,
+                             float *norm);
+
 /* Attach a network to a context (NULL detaches).  A step on a context with a
  * network starts the multi-direct forcing from the network's prediction: one
  * interpolation pass of u-hat computes each marker's features, evaluates the

@@ -33,6 +33,7 @@ EXPORTS = ("prs_create", "prs_destroy", "prs_last_error", "prs_template", "prs_i
            "prs_timing_read", "prs_mlp_create", "prs_mlp_destroy", "prs_mlp_last_error",
            "prs_mlp_get", "prs_mlp_forward", "prs_mlp_backward", "prs_mlp_adam",
            "prs_mlp_train_step", "prs_mlp_loss", "prs_mlp_standardize", "prs_mlp_fit_norm",
+           "prs_mlp_fit_norm_noalloc",
            "prs_set_learned", "prs_forcing_samples")
 MLP_PARAMS = 6288
 MLP_NORM = 38
@@ -145,6 +146,7 @@ def lib():
         L.prs_mlp_loss.argtypes = [vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_double)]
         L.prs_mlp_standardize.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp]
         L.prs_mlp_fit_norm.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.prs_mlp_fit_norm_noalloc.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.prs_mlp_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float,
                                          C.POINTER(C.c_double)]
         _lib = L
@@ -559,17 +561,18 @@ class Mlp:
         return Xs, Ts
 
     @staticmethod
-    def fit_norm(X, T):
+    def fit_norm(X, T, noalloc: bool = False):
         """Normalisation vector (feature mean/std, target mean/std) of raw
-        samples X [m, 16], T [m, 3] on the device (prs_mlp_fit_norm)."""
+        samples X [m, 16], T [m, 3] on the device (prs_mlp_fit_norm, or its
+        allocation-free variant prs_mlp_fit_norm_noalloc)."""
         import numpy as np
 
         m = X.shape[0]
         Mlp._chk(X, (m, 16), "X")
         Mlp._chk(T, (m, 3), "T")
         nv = np.zeros(MLP_NORM, np.float32)
-        rc = lib().prs_mlp_fit_norm(_stream_ptr(), _ptr(X), _ptr(T), m,
-                                    C.c_void_p(nv.ctypes.data))
+        fn = lib().prs_mlp_fit_norm_noalloc if noalloc else lib().prs_mlp_fit_norm
+        rc = fn(_stream_ptr(), _ptr(X), _ptr(T), m, C.c_void_p(nv.ctypes.data))
         if rc != PRS_OK:
-            raise PrsError(rc, "prs_mlp_fit_norm failed")
+            raise PrsError(rc, "prs_mlp_fit_norm%s failed" % ("_noalloc" if noalloc else ""))
         return nv

@@ -2,6 +2,7 @@
 // marker-forcing network on MFMA, and its extern "C" entry points.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "prs_internal.h"
@@ -465,6 +466,33 @@ int fit_norm_with(hipStream_t s, const float *X, const float *T, int64_t count, 
   return PRS_OK;
 }
 
+// Scratch of prs_mlp_fit_norm_noalloc: the per-block partial sums and the
+// statistics.  Every device the library runs on holds its own instance of
+// this array until the process ends; host code never passes its name to a
+// kernel (on the host the name is only a stand-in), but the device address
+// looked up once per device with that device current.
+constexpr int kNoAllocDoubles = kStatBlocks * kStatCols + 2 * kStatCols;
+__device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+int scratch_address(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PRS_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PRS_EHIP;
+    g_scratch[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch[dev];
+  return PRS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +636,14 @@ int prs_mlp_fit_norm(void *stream, const float *X, const float *T, int64_t count
   (void)hipFree(part);
   (void)hipFree(stat);
   return rc;
+}
+
+int prs_mlp_fit_norm_noalloc(void *stream, const float *X, const float *T, int64_t count,
+                             float *norm) {
+  if (count < 2 || !X || !T || !norm) return PRS_EINVAL;
+  double *base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  return fit_norm_with(st(stream), X, T, count, base, base + kStatBlocks * kStatCols, norm);
 }
 
 }  // extern "C"
