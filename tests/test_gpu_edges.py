@@ -1,7 +1,8 @@
 """Edge cases of the step against the oracle (FP64 1e-11, FP32 1e-5):
 marker counts at the extremes of a workgroup (a ragged 37, exactly one
-wave, the maximum 1024), and the three brick shapes of the interpolation (15 and 21
-nodes, compiled with the edge known, and 17, the general path)."""
+wave, the maximum 1024), and the brick shapes of the interpolation (14 nodes
+at D/h = 10 and 20 at D/h = 16, compiled with the edge known, and 16 at
+D/h = 12, the general path)."""
 import numpy as np
 import pytest
 
@@ -75,7 +76,7 @@ def test_marker_count_extremes(P, orc, nl, precision):
     check(gpu, ref, TOL[precision])
 
 
-@pytest.mark.parametrize("d_over_h,nl", [(16, 804), (12, 452)], ids=["brick21", "brick17"])
+@pytest.mark.parametrize("d_over_h,nl", [(16, 804), (12, 452)], ids=["brick20", "brick16"])
 @pytest.mark.parametrize("precision", [1, 0])
 def test_brick_shapes(P, orc, d_over_h, nl, precision):
     w = W.small(f"dh{d_over_h}", 30, 8, (4.0, 5.0, 4.0), d_over_h=d_over_h, n_markers=nl,
