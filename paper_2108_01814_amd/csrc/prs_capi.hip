@@ -392,7 +392,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   (void)hipGetDevice(&c->device);
   {
     hipDeviceProp_t prop;
-    const size_t need = brick_bytes(nb, q.precision == PRS_F64 ? 8 : 4) + 4096;
+    const size_t need = interp_lds_bytes(nb, q.precision == PRS_F64 ? 8 : 4) + 4096;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && need > prop.sharedMemPerBlock) {
       delete c;
       return PRS_EINVAL;
@@ -475,7 +475,7 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     // later passes of a step: 2048 markers and 256 candidate spheres per tile
     // (a tile with more is culled again instead)
     const int ntiles = esz == 8 ? spread_tile_count<double>(c->G) : spread_tile_count<float>(c->G);
-    S.tc_cap = 2048 + 256;
+    S.tc_cap = kTileRecord;
     rc |= alloc(c, &S.tc_items, (size_t)ntiles * S.tc_cap);
     rc |= alloc(c, &S.tc_count, (size_t)ntiles);
     rc |= alloc(c, &S.tc_ncand, (size_t)ntiles);
@@ -810,8 +810,8 @@ int prs_set_learned(prs_ctx *c, const prs_mlp *mlp) {
   if (!c) return PRS_EINVAL;
   if (mlp) {
     const int nb = brick_edge(c->p.radius, c->p.h);
-    const size_t brick = brick_bytes(nb, c->p.precision == PRS_F64 ? 8 : 4);
-    const size_t need = std::max(brick, learned_lds_bytes(c->p.n_markers)) + 4096;
+    const size_t need =
+        learned_lds_bytes(c->p.n_markers, nb, c->p.precision == PRS_F64 ? 8 : 4) + 4096;
     hipDeviceProp_t prop;
     HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
     if (need > prop.sharedMemPerBlock)

@@ -97,12 +97,36 @@ size_t brick_bytes(int nb, int esz) {
          esz;
 }
 
+// Interpolation brick chunks loaded straight into LDS (1) or through
+// registers (0).
+#ifndef PRS_INTERP_DMA
+#define PRS_INTERP_DMA 1
+#endif
+
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
-size_t learned_lds_bytes(int nl) {
-  const size_t per = (size_t)block_for(nl) * (kMlpIn * sizeof(unsigned short) +
-                                               kMlpUsed * sizeof(float));
-  return kMlpLdsBytes + ((per + 15) & ~(size_t)15) + kGeluTabN * sizeof(float4);
+// Brick buffers of the interpolation: two (the next component's brick loads
+// while the current one's stencils run) when they take at most 32 KB of LDS,
+// else one (the occupancy is worth more than the overlap).
+int interp_brick_buffers(int nb, int esz) {
+  return PRS_INTERP_DMA && 2 * brick_bytes(nb, esz) <= 32768 ? 2 : 1;
+}
+
+size_t interp_lds_bytes(int nb, int esz) { return brick_bytes(nb, esz) * interp_brick_buffers(nb, esz); }
+
+// LDS of the fused learned pass: the brick buffers, later reused for the
+// network's standardised inputs (BF16) and predictions (FP32) of the block's
+// markers, then the forward weights and the GELU table (staged at the start,
+// while the bricks load).
+__host__ __device__ inline size_t learned_io_region(int block, size_t bricks) {
+  const size_t io = ((size_t)block * (kMlpIn * sizeof(unsigned short) + kMlpUsed * sizeof(float)) +
+                     15) & ~(size_t)15;
+  return bricks > io ? bricks : io;
+}
+
+size_t learned_lds_bytes(int nl, int nb, int esz) {
+  return learned_io_region(block_for(nl), interp_lds_bytes(nb, esz)) + kMlpFwdLdsBytes +
+         kGeluTabN * sizeof(float4);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,6 +173,15 @@ struct BrickSlots {
 
 // NB: brick edge known at compile time (14 at D/h = 10, 20 at D/h = 16) or 0
 // for the runtime edge nb.
+// 16 bytes per lane from global memory straight into LDS: lane i of the wave
+// writes at wave_base + 16 i (wave_base uniform across the wave).
+__device__ inline void lds_load16(const void *src, void *wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)wave_base, 16,
+                                   0, 0);
+}
+// Waits until this wave's memory operations have completed.
+__device__ inline void wait_loads() { __builtin_amdgcn_s_waitcnt(0); }
+
 template <typename T, int MODE, int NB>
 __global__ __launch_bounds__(1024) void k_interp(
     Geom G, const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ a0,
@@ -157,22 +190,261 @@ __global__ __launch_bounds__(1024) void k_interp(
     const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
     T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
     double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la,
-    float *__restrict__ vmax_out, T *__restrict__ u0) {
+    float *__restrict__ vmax_out, T *__restrict__ u0, int nbuf) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *brick = reinterpret_cast<T *>(smem_raw);
   if (NB > 0) nb = NB;
+  // the workgroup size and this wave's first thread, read once (blockDim is
+  // otherwise reloaded from the dispatch packet, and that load's wait would
+  // also wait for the brick loads in flight)
+  const int bdim = (int)blockDim.x;
+  const int wave_base = (int)(threadIdx.x & ~63u);
   const int p = xcd_item(blockIdx.x, n);
   if (p < 0) return;
   const bool active = (int)threadIdx.x < G.nl;
   const int l = active ? order[threadIdx.x] : 0;
   const size_t N = (size_t)n;
 
-  double xp[3], up[3] = {0, 0, 0}, wp[3] = {0, 0, 0};
-  if (MODE == kInterpPlain) {
+  // the sphere's node, staggered fractions and brick origin (the rest of
+  // the sphere's state is read once the field is interpolated)
+  int lo[3];
+  T fo[3][2];
+  const int E = brick_reach(G.R, G.h);
+  {
     uint32_t fl = 0;
-    xp[0] = sane_coord(xs[3 * p + 0], G.Lx, false, fl);
-    xp[1] = sane_coord(xs[3 * p + 1], G.Ly, true, fl);
-    xp[2] = sane_coord(xs[3 * p + 2], G.Lz, false, fl);
+    for (int a = 0; a < 3; ++a) {
+      const double xa = MODE == kInterpPlain
+                            ? sane_coord(xs[3 * p + a], a == 0 ? G.Lx : (a == 1 ? G.Ly : G.Lz),
+                                         a == 1, fl)
+                            : xs[a * N + p];
+      int Ia;
+      sphere_axis<T>(xa, G.inv_h, Ia, fo[a]);
+      lo[a] = Ia - E;
+    }
+  }
+  const T tadt = (T)adt;
+  // An MDF pass over a nonzero f interpolates f alone and adds the step's
+  // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
+  // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
+  // that interpolate u-hat record it in u0.
+  const bool f_only = MODE == kInterpMDF && b0 != nullptr;
+  T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
+  if (active) MarkerOffset<T>::load(tm, l, mhi, mlo);
+
+  constexpr int VEC = 16 / sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  const int P = brick_pitch_c<T>(nb);
+  const int CPR = P / VEC;
+  const int per_comp = nb * nb * CPR;
+  // the fused learned pass: the network's weights and GELU table, staged now
+  // so that their loads overlap the bricks'
+  unsigned char *const learned_base =
+      smem_raw + learned_io_region(bdim, (size_t)nbuf * per_comp * 16);
+  // the reciprocals of the features' standard deviations (standardisation
+  // by multiplication; within an FP64 rounding of the quotient)
+  __shared__ double s_istd[kMlpFeat];
+  if constexpr (MODE == kInterpLearned) {
+    if ((int)threadIdx.x < kMlpFeat) s_istd[threadIdx.x] = 1.0 / (double)la.norm[kMlpIn + threadIdx.x];
+    mlp_stage_fwd(*reinterpret_cast<MlpFwdLds *>(learned_base), la.wbf, la.master);
+    float4 *gtab = reinterpret_cast<float4 *>(learned_base + kMlpFwdLdsBytes);
+    for (int i = threadIdx.x; i < kGeluTabN; i += bdim)
+      gtab[i] = reinterpret_cast<const float4 *>(la.gelu_tab)[i];
+  }
+  // this lane's chunk slots, the same for the three components (their
+  // bricks share the origin), two registers each: the node plane k (wrapped)
+  // with flags in the top bits (bit 28: row inside the fluid for u and w,
+  // bit 29: for v, bit 30: the chunk crosses the periodic x seam, bit 31:
+  // slot in use), and the offset j nx + x0 of the chunk within the plane
+  constexpr int kSlots = BrickSlots<T>::value;
+  constexpr unsigned kFuw = 1u << 28, kFv = 1u << 29, kFseam = 1u << 30, kFuse = 1u << 31;
+  unsigned sK[kSlots];
+  int sJX[kSlots];
+#pragma unroll
+  for (int u = 0; u < kSlots; ++u) {
+    const int it = threadIdx.x + u * bdim;
+    const int row = it / CPR, ch = it - row * CPR;
+    const int bz = row / nb, by = row - bz * nb;
+    const int j = lo[1] + by;
+    const int x0 = lo[0] + ch * VEC;
+    sK[u] = (unsigned)wrap_once(lo[2] + bz, G.nz) | (j >= 0 && j <= G.ny - 1 ? kFuw : 0u) |
+            (j >= 1 && j <= G.ny - 1 ? kFv : 0u) |
+            (x0 < 0 || x0 + VEC > G.nx ? kFseam : 0u) | (it < per_comp ? kFuse : 0u);
+    sJX[u] = j * G.nx + x0;
+  }
+  // rows per node plane of component c (v has ny + 1 rows)
+  auto nyc = [&](int c) { return c == 1 ? G.ny + 1 : G.ny; };
+  auto load_slot = [&](int c, int u) {
+    vec_t v = (vec_t)(T)0;
+    const unsigned fl = sK[u];
+    if ((fl & kFuse) && (fl & (c == 1 ? kFv : kFuw))) {
+      const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
+      const size_t plane = (size_t)(fl & (kFuw - 1u)) * (size_t)nyc(c) * (size_t)G.nx;
+      if (!(fl & kFseam)) {
+        __builtin_memcpy(&v, Sp + plane + (size_t)(long)sJX[u], sizeof(vec_t));
+      } else {
+        // the chunk crosses the seam: elements wrapped one by one
+        const int it = threadIdx.x + u * bdim;
+        const int row = it / CPR, ch = it - row * CPR;
+        const int by = row - (row / nb) * nb;
+        const T *rowp = Sp + plane + (size_t)(long)((lo[1] + by) * G.nx);
+        const int x0 = lo[0] + ch * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(x0 + e, G.nx)];
+      }
+    }
+    return v;
+  };
+  auto store_slot = [&](int u, vec_t v) {
+    const int it = threadIdx.x + u * bdim;
+    if (it < per_comp) {
+      const int row = it / CPR, ch = it - row * CPR;
+      *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
+    }
+  };
+  T U[3] = {(T)0, (T)0, (T)0};
+  // the field of component c that this pass interpolates
+  auto field = [&](int c) {
+    return f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
+  };
+  // Component c's brick in buf, straight from memory (kDma): each chunk
+  // inside the fluid and clear of the x seam goes into LDS without passing
+  // through registers (global_load_lds_dwordx4: lane i of a wave writes the
+  // 16 bytes at LDS base + 16 i, and chunk it = slot u * blockDim + wave * 64
+  // + lane sits at byte 16 it of the brick); the other chunks are stored by
+  // their lanes (zeros, or the wrapped elements at the seam).  Completes at
+  // the caller's wait_loads.
+  // The lanes' own stores come first (the seam chunks wait for their loads,
+  // which would otherwise also wait for the direct loads in flight), then
+  // the direct loads.
+  auto dma_component = [&](int c, T *buf) {
+    const T *Sp = field(c);
+    const unsigned in_flag = c == 1 ? kFv : kFuw;
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+      const unsigned fl = sK[u];
+      if ((fl & kFuse) && !(fl & in_flag))
+        *reinterpret_cast<vec_t *>(buf + (threadIdx.x + u * bdim) * VEC) = (vec_t)(T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+      const unsigned fl = sK[u];
+      if ((fl & kFuse) && (fl & in_flag) && (fl & kFseam))
+        *reinterpret_cast<vec_t *>(buf + (threadIdx.x + u * bdim) * VEC) = load_slot(c, u);
+    }
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+      const unsigned fl = sK[u];
+      if ((fl & kFuse) && (fl & in_flag) && !(fl & kFseam)) {
+        const size_t plane = (size_t)(fl & (kFuw - 1u)) * (size_t)nyc(c) * (size_t)G.nx;
+        lds_load16(Sp + plane + (size_t)(long)sJX[u], buf + (u * bdim + wave_base) * VEC);
+      }
+    }
+  };
+  // Component c interpolated from its brick: the three axis stencils, then
+  // the 27-point sum contracted separably (x, then y, then z).  Selects
+  // rather than indexing by c keep the arrays in registers.
+  auto stencil_component = [&](int c, const T *buf) {
+    if (!active) return;
+    T wx[3], wy[3], wz[3];
+    const T f0 = c == 0 ? fo[0][0] : fo[0][1];   // fo[0][stag(c, 0)]
+    const T f1 = c == 1 ? fo[1][0] : fo[1][1];   // fo[1][stag(c, 1)]
+    const T f2 = c == 2 ? fo[2][0] : fo[2][1];   // fo[2][stag(c, 2)]
+    const int bx = min(max(stencil_axis<T>(f0, mhi[0], mlo[0], wx) - 1 + E, 0), nb - 3);
+    const int by = min(max(stencil_axis<T>(f1, mhi[1], mlo[1], wy) - 1 + E, 0), nb - 3);
+    const int bz = min(max(stencil_axis<T>(f2, mhi[2], mlo[2], wz) - 1 + E, 0), nb - 3);
+    const T *bk = buf + ((bz * nb + by) * P + bx);
+    T zsum = 0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      T ysum = 0;
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        const T *row = bk + (kk * nb + jj) * P;
+        const T xsum = fma(row[2], wx[2], fma(row[1], wx[1], row[0] * wx[0]));
+        ysum = fma(wy[jj], xsum, ysum);
+      }
+      zsum = fma(wz[kk], ysum, zsum);
+    }
+    U[0] = c == 0 ? zsum : U[0];
+    U[1] = c == 1 ? zsum : U[1];
+    U[2] = c == 2 ? zsum : U[2];
+  };
+  // When the lane's slots cover the brick: direct loads into two LDS
+  // buffers, the next component's brick in flight while the current one's
+  // stencils run (without direct loads, the next component's chunks wait in
+  // registers meanwhile).  With few markers per sphere each component is
+  // loaded in rounds of blockDim.
+  const bool pipe = per_comp <= kSlots * bdim;
+  constexpr bool kDma = PRS_INTERP_DMA != 0;
+  if (pipe && kDma && nbuf == 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();   // the previous component's brick is no longer read
+      dma_component(c, brick);
+      wait_loads();
+      __syncthreads();
+      stencil_component(c, brick);
+    }
+  } else if (pipe && kDma) {
+    T *buf[2] = {brick, brick + per_comp * VEC};
+    dma_component(0, buf[0]);
+    wait_loads();
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // buf[(c + 1) & 1] was last read by component c - 1, before the
+      // barrier that ended the previous round
+      if (c < 2) dma_component(c + 1, buf[(c + 1) & 1]);
+      stencil_component(c, buf[c & 1]);
+      if (c < 2) {
+        wait_loads();
+        __syncthreads();
+      }
+    }
+  } else {
+    vec_t nxt[kSlots];
+    if (pipe) {
+#pragma unroll
+      for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(0, u);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();   // the previous component's brick is no longer read
+      if (pipe) {
+#pragma unroll
+        for (int u = 0; u < kSlots; ++u) store_slot(u, nxt[u]);
+        if (c < 2) {
+#pragma unroll
+          for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(c + 1, u);
+        }
+      } else {
+        const T *Sp = field(c);
+        for (int it = threadIdx.x; it < per_comp; it += bdim) {
+          const int row = it / CPR, ch = it - row * CPR;
+          const int bz = row / nb, by = row - bz * nb;
+          const int j = lo[1] + by, x0 = lo[0] + ch * VEC;
+          vec_t v = (vec_t)(T)0;
+          if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
+            const int k = wrap_once(lo[2] + bz, G.nz);
+            const T *rowp = Sp + ((size_t)k * (size_t)nyc(c) + (size_t)j) * (size_t)G.nx;
+            if (x0 >= 0 && x0 + VEC <= G.nx) {
+              __builtin_memcpy(&v, rowp + x0, sizeof(vec_t));
+            } else {
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(x0 + e, G.nx)];
+            }
+          }
+          *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
+        }
+      }
+      __syncthreads();
+      stencil_component(c, brick);
+    }
+  }
+
+  // the sphere's velocities and the marker's lever arm and rigid velocity
+  double up[3] = {0, 0, 0}, wp[3] = {0, 0, 0};
+  if (MODE == kInterpPlain) {
     if (out2)
       for (int a = 0; a < 3; ++a) {
         up[a] = us[3 * p + a];
@@ -180,7 +452,6 @@ __global__ __launch_bounds__(1024) void k_interp(
       }
   } else {
     for (int a = 0; a < 3; ++a) {
-      xp[a] = xs[a * N + p];
       up[a] = us[a * N + p];
       wp[a] = ws[a * N + p];
     }
@@ -191,145 +462,6 @@ __global__ __launch_bounds__(1024) void k_interp(
   const double Ud[3] = {up[0] + (wp[1] * rl[2] - wp[2] * rl[1]),
                         up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
-  const T tadt = (T)adt;
-  // An MDF pass over a nonzero f interpolates f alone and adds the step's
-  // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
-  // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
-  // that interpolate u-hat record it in u0.
-  const bool f_only = MODE == kInterpMDF && b0 != nullptr;
-
-  // the sphere's node, staggered fractions and brick origin
-  int I[3], lo[3];
-  T fo[3][2];
-  const int E = brick_reach(G.R, G.h);
-  for (int a = 0; a < 3; ++a) {
-    sphere_axis<T>(xp[a], G.inv_h, I[a], fo[a]);
-    lo[a] = I[a] - E;
-  }
-  // the marker's six axis stencils (three axes, two staggerings): brick
-  // index of the first node and the weights
-  int bs[3][2];
-  T w[3][2][3];
-  {
-    T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
-    if (active) MarkerOffset<T>::load(tm, l, mhi, mlo);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int o = 0; o < 2; ++o) {
-        const int c = stencil_axis<T>(fo[a][o], mhi[a], mlo[a], w[a][o]);
-        bs[a][o] = min(max(c - 1 + E, 0), nb - 3);
-      }
-  }
-
-  constexpr int VEC = 16 / sizeof(T);
-  typedef T vec_t __attribute__((ext_vector_type(VEC)));
-  const int P = brick_pitch_c<T>(nb);
-  const int CPR = P / VEC;
-  const int per_comp = nb * nb * CPR;
-  // this lane's chunk slots, the same for the three components (their
-  // bricks share the origin): node plane k (wrapped), row offset j nx, first
-  // x node x0, and flags (bit 0: row inside the fluid for u and w, bit 1: for
-  // v, bit 2: the chunk crosses the periodic x seam, bit 3: slot in use)
-  constexpr int kSlots = BrickSlots<T>::value;
-  int sK[kSlots], sJ[kSlots], sX[kSlots], sF[kSlots];
-#pragma unroll
-  for (int u = 0; u < kSlots; ++u) {
-    const int it = threadIdx.x + u * blockDim.x;
-    const int row = it / CPR, ch = it - row * CPR;
-    const int bz = row / nb, by = row - bz * nb;
-    const int j = lo[1] + by;
-    const int x0 = lo[0] + ch * VEC;
-    sK[u] = wrap_once(lo[2] + bz, G.nz);
-    sJ[u] = j * G.nx;
-    sX[u] = x0;
-    sF[u] = (j >= 0 && j <= G.ny - 1 ? 1 : 0) | (j >= 1 && j <= G.ny - 1 ? 2 : 0) |
-            (x0 < 0 || x0 + VEC > G.nx ? 4 : 0) | (it < per_comp ? 8 : 0);
-  }
-  const int nyc_[3] = {G.ny, G.ny + 1, G.ny};
-  auto load_slot = [&](int c, int u) {
-    vec_t v = (vec_t)(T)0;
-    const int fl = sF[u];
-    if ((fl & 8) && (fl & (c == 1 ? 2 : 1))) {
-      const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
-      const T *rowp = Sp + ((size_t)sK[u] * (size_t)nyc_[c] * (size_t)G.nx + (size_t)sJ[u]);
-      if (!(fl & 4)) {
-        __builtin_memcpy(&v, rowp + sX[u], sizeof(vec_t));
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(sX[u] + e, G.nx)];
-      }
-    }
-    return v;
-  };
-  auto store_slot = [&](int u, vec_t v) {
-    const int it = threadIdx.x + u * blockDim.x;
-    if (it < per_comp) {
-      const int row = it / CPR, ch = it - row * CPR;
-      *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
-    }
-  };
-  T U[3] = {(T)0, (T)0, (T)0};
-  // software pipeline (when the lane's slots cover the brick): the next
-  // component's chunks are loaded into registers while the current
-  // component's stencils run; otherwise (few markers per sphere) each
-  // component's brick is loaded in rounds of blockDim chunks
-  const bool pipe = per_comp <= kSlots * (int)blockDim.x;
-  vec_t nxt[kSlots];
-  if (pipe) {
-#pragma unroll
-    for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(0, u);
-  }
-  for (int c = 0; c < 3; ++c) {
-    __syncthreads();   // the previous component's brick is no longer read
-    if (pipe) {
-#pragma unroll
-      for (int u = 0; u < kSlots; ++u) store_slot(u, nxt[u]);
-      if (c < 2) {
-#pragma unroll
-        for (int u = 0; u < kSlots; ++u) nxt[u] = load_slot(c + 1, u);
-      }
-    } else {
-      const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
-      for (int it = threadIdx.x; it < per_comp; it += blockDim.x) {
-        const int row = it / CPR, ch = it - row * CPR;
-        const int bz = row / nb, by = row - bz * nb;
-        const int j = lo[1] + by, x0 = lo[0] + ch * VEC;
-        vec_t v = (vec_t)(T)0;
-        if (j >= (c == 1 ? 1 : 0) && j <= G.ny - 1) {
-          const int k = wrap_once(lo[2] + bz, G.nz);
-          const T *rowp = Sp + ((size_t)k * (size_t)nyc_[c] + (size_t)j) * (size_t)G.nx;
-          if (x0 >= 0 && x0 + VEC <= G.nx) {
-            __builtin_memcpy(&v, rowp + x0, sizeof(vec_t));
-          } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = rowp[wrap_once(x0 + e, G.nx)];
-          }
-        }
-        *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
-      }
-    }
-    __syncthreads();
-    if (active) {
-      // the 27-point sum contracted separably (x, then y, then z)
-      const int ox = stag(c, 0), oy = stag(c, 1), oz = stag(c, 2);
-      const T *bk = brick + ((bs[2][oz] * nb + bs[1][oy]) * P + bs[0][ox]);
-      const T *wx = w[0][ox], *wy = w[1][oy], *wz = w[2][oz];
-      T zsum = 0;
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) {
-        T ysum = 0;
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-          const T *row = bk + (kk * nb + jj) * P;
-          const T xsum = fma(row[2], wx[2], fma(row[1], wx[1], row[0] * wx[0]));
-          ysum = fma(wy[jj], xsum, ysum);
-        }
-        zsum = fma(wz[kk], ysum, zsum);
-      }
-      U[c] = zsum;
-    }
-  }
 
   if (MODE != kInterpPlain && active && u0) {
     const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
@@ -370,16 +502,13 @@ __global__ __launch_bounds__(1024) void k_interp(
     // the network on the matrix cores: each wave evaluates its 64 markers as
     // four 16-marker tiles.  The brick's LDS is reused for the weights, the
     // standardised inputs (BF16) and the predictions (FP32).
-    MlpLds &L = *reinterpret_cast<MlpLds *>(smem_raw);
+    const MlpFwdLds &L = *reinterpret_cast<const MlpFwdLds *>(learned_base);
+    const float4 *gtab = reinterpret_cast<const float4 *>(learned_base + kMlpFwdLdsBytes);
     // input fragments, tile-major: entry [tile][16 q + r] holds features
     // 4q .. 4q+3 of marker r of the tile (tile = 16 consecutive lanes)
-    bf16x4 *fl = reinterpret_cast<bf16x4 *>(smem_raw + kMlpLdsBytes);
-    float *yl = reinterpret_cast<float *>(fl + blockDim.x * (kMlpIn / 4));
-    float4 *gtab = reinterpret_cast<float4 *>(yl + blockDim.x * kMlpUsed);
-    __syncthreads();   // the brick is no longer read
-    mlp_stage(L, la.wbf, la.master, false);
-    for (int i = threadIdx.x; i < kGeluTabN; i += blockDim.x)
-      gtab[i] = reinterpret_cast<const float4 *>(la.gelu_tab)[i];
+    bf16x4 *fl = reinterpret_cast<bf16x4 *>(smem_raw);
+    float *yl = reinterpret_cast<float *>(fl + bdim * (kMlpIn / 4));
+    __syncthreads();   // the bricks are no longer read
     {
       const int tile = threadIdx.x >> 4, r = threadIdx.x & 15;
       for (int q = 0; q < kMlpIn / 4; ++q) {
@@ -387,7 +516,7 @@ __global__ __launch_bounds__(1024) void k_interp(
         for (int j = 0; j < 4; ++j) {
           const int k = 4 * q + j;
           v[j] = (active && k < kMlpFeat)
-                     ? (float)((featd[k] - (double)la.norm[k]) / (double)la.norm[kMlpIn + k])
+                     ? (float)((featd[k] - (double)la.norm[k]) * s_istd[k])
                      : 0.f;
         }
         fl[tile * 64 + 16 * q + r] = pack4(v[0], v[1], v[2], v[3]);
@@ -406,11 +535,12 @@ __global__ __launch_bounds__(1024) void k_interp(
     if (active) {
       // de-standardise in FP64: F0 = (y std + mean) / (alpha dt)
       const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
+      const double inv_adt = 1.0 / adt;
       double d[3];
       for (int c = 0; c < 3; ++c) {
         const double y = (double)yl[threadIdx.x * kMlpUsed + c];
         const T f0 = (T)((y * (double)la.norm[2 * kMlpIn + kMlpUsed + c] +
-                          (double)la.norm[2 * kMlpIn + c]) / adt);
+                          (double)la.norm[2 * kMlpIn + c]) * inv_adt);
         out[c * M + m] = f0;
         vm = nan_max(vm, fabsf((float)f0));
         d[c] = (double)f0;
@@ -474,13 +604,14 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const Scratch &S, con
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
   const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
-  size_t lds = brick_bytes(nb, sizeof(T));
-  if (MODE == kInterpLearned) lds = std::max(lds, learned_lds_bytes(G.nl));
+  const int nbuf = interp_brick_buffers(nb, sizeof(T));
+  size_t lds = brick_bytes(nb, sizeof(T)) * nbuf;
+  if (MODE == kInterpLearned) lds = learned_lds_bytes(G.nl, nb, sizeof(T));
   const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
 #define PRS_LAUNCH_INTERP(NBV)                                                                 \
   hipLaunchKernelGGL((k_interp<T, MODE, NBV>), grid, block, lds, s, G, S.templ, tm, a0, a1, a2, \
                      b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part,        \
-                     S.lane_order, la, vmax_out, u0)
+                     S.lane_order, la, vmax_out, u0, nbuf)
   if (nb == 14)
     PRS_LAUNCH_INTERP(14);
   else if (nb == 20)
@@ -627,15 +758,26 @@ struct TileAcc<float> {
   using type = int;
 };
 
-// Guard band of the accumulators: two nodes on every side of the tile.  A
-// marker's component is accumulated when its 3-node stencil meets the tile
-// along every axis, so its nodes lie within the band, and all 27 adds run
-// without per-node tests (the band's sums are discarded).
+// Accumulator layout of a tile: per component TZ planes of TY x-rows, each
+// row TX + 2 kGuard entries long.  A marker's component is accumulated when
+// its 3-node stencil meets the tile along every axis; its rows outside the
+// tile in y or z are skipped (one test per row), and along x the row carries
+// a guard band of two nodes on each side, so the three adds of a row run
+// without tests (the band's sums are discarded).  Only the tile's own rows
+// take LDS, which keeps three tiles resident per compute unit.
 constexpr int kGuard = 2;
+template <int TX, int TY, int TZ>
+struct AccLayout {
+  static constexpr int PX = TX + 2 * kGuard;
+  static constexpr int NODES = PX * TY * TZ;   // per component
+};
 
 constexpr int kTileCand = 256;     // spheres gathered by one tile
 constexpr int kTileThreads = PRS_TILE_THREADS;
 constexpr int kTileList = 1024;    // culled markers buffered before accumulation
+// Rounds of the block over a tile's recorded markers (a record holds at
+// most kTileRecord entries: candidates, then markers).
+constexpr int kReplayRounds = (kTileRecord + PRS_TILE_THREADS - 1) / PRS_TILE_THREADS;
 static_assert(kTileThreads >= kTileCand && kTileCand % 64 == 0, "one scan lane per candidate");
 static_assert(kTileList >= 2 * kTileThreads, "a round must fit after a flush check");
 static_assert(kMaxMarkers <= 1024, "list code: candidate << 10 | marker");
@@ -670,19 +812,32 @@ __device__ inline void tile_cand(const Geom &G, double x, double y, double z, in
   }
 }
 
+// Fixed-point rounding of one contribution: floor(x + 1/2) in one
+// instruction (the sums stay exact integers, so their order does not matter;
+// ties round up rather than to even).
+__device__ inline int fixed_round(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// Clears the tile accumulators with 16-byte stores.
+template <typename A_t, int COUNT>
+__device__ inline void acc_clear(A_t *acc) {
+  static_assert((COUNT * sizeof(A_t)) % 16 == 0, "accumulators in 16-byte chunks");
+  constexpr int kChunks = COUNT * sizeof(A_t) / 16;
+  uint4 *p = reinterpret_cast<uint4 *>(acc);
+  for (int q = threadIdx.x; q < kChunks; q += blockDim.x) p[q] = make_uint4(0, 0, 0, 0);
+}
+
 // One marker's contribution to a tile: the six axis stencils, and for each
 // component whose stencil meets the tile, its 27 adds of
 // value * weight * dV / h^3 into the guard-banded accumulator.
 // scale: dV / h^3 (floating-point accumulators) or dV / h^3 / unit (fixed point).
-template <typename T, int SRC, int TX, int TY, int TZ>
-__device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3][2],
-                                    const T *__restrict__ tm, const T *__restrict__ src,
-                                    const int *__restrict__ perm, int k, int l, size_t M, T scale,
-                                    typename TileAcc<T>::type *acc) {
-  using A_t = typename TileAcc<T>::type;
-  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
-  constexpr int NODES_P = PX * PY * PZ;
-  T v[3];
+// The marker's three values (marker l of sorted sphere k).
+template <typename T, int SRC>
+__device__ inline void marker_values(const Geom &G, const T *__restrict__ src,
+                                     const int *__restrict__ perm, int k, int l, size_t M, T v[3]) {
   if (SRC == 0) {
     const size_t m = (size_t)k * G.nl + l;
     for (int c = 0; c < 3; ++c) v[c] = src[c * M + m];
@@ -690,6 +845,21 @@ __device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3]
     const size_t m = (size_t)perm[k] * G.nl + l;
     for (int c = 0; c < 3; ++c) v[c] = src[3 * m + c];
   }
+}
+
+template <typename T, int SRC, int TX, int TY, int TZ>
+__device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3][2],
+                                    const T *__restrict__ tm, const T *__restrict__ src,
+                                    const int *__restrict__ perm, int k, int l, size_t M, T scale,
+                                    typename TileAcc<T>::type *acc);
+
+// The same with the marker's values already loaded.
+template <typename T, int TX, int TY, int TZ>
+__device__ inline void spread_visit_v(const Geom &G, const int d[3], const T fo[3][2],
+                                      const T *__restrict__ tm, const T v[3], int l, T scale,
+                                      typename TileAcc<T>::type *acc) {
+  using A_t = typename TileAcc<T>::type;
+  constexpr int PX = AccLayout<TX, TY, TZ>::PX, NODES = AccLayout<TX, TY, TZ>::NODES;
   T mhi[3], mlo[3];
   MarkerOffset<T>::load(tm, l, mhi, mlo);
   int b[3][2];
@@ -705,26 +875,41 @@ __device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3]
     const int bx = b[0][ox], by = b[1][oy], bz = b[2][oz];
     // nodes b .. b + 2 (guard-banded index) meet the tile's b in [0, T + 1]
     if (!((unsigned)bx <= lim[0] && (unsigned)by <= lim[1] && (unsigned)bz <= lim[2])) continue;
-    A_t *A = acc + c * NODES_P + (bz * PY + by) * PX + bx;
+    // the stencil's first row and plane in tile coordinates (-2 .. T - 1)
+    const int y0 = by - kGuard, z0 = bz - kGuard;
+    A_t *Ac = acc + c * NODES + bx;
     using W_t = typename std::conditional<std::is_integral<A_t>::value, T, A_t>::type;
     const W_t val = (W_t)(v[c] * scale);
     const T *wx = w[0][ox], *wy = w[1][oy], *wz = w[2][oz];
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
+      if ((unsigned)(z0 + kk) >= (unsigned)TZ) continue;
       const W_t vz = val * (W_t)wz[kk];
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) {
+        if ((unsigned)(y0 + jj) >= (unsigned)TY) continue;
         const W_t vzy = vz * (W_t)wy[jj];
+        A_t *row = Ac + ((z0 + kk) * TY + (y0 + jj)) * PX;
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
           if constexpr (std::is_integral<A_t>::value)
-            atomicAdd(A + (kk * PY + jj) * PX + ii, (A_t)__float2int_rn(vzy * (W_t)wx[ii]));
+            atomicAdd(row + ii, fixed_round(vzy * (W_t)wx[ii]));
           else
-            atomicAdd(A + (kk * PY + jj) * PX + ii, vzy * (W_t)wx[ii]);
+            atomicAdd(row + ii, vzy * (W_t)wx[ii]);
         }
       }
     }
   }
+}
+
+template <typename T, int SRC, int TX, int TY, int TZ>
+__device__ inline void spread_visit(const Geom &G, const int d[3], const T fo[3][2],
+                                    const T *__restrict__ tm, const T *__restrict__ src,
+                                    const int *__restrict__ perm, int k, int l, size_t M, T scale,
+                                    typename TileAcc<T>::type *acc) {
+  T v[3];
+  marker_values<T, SRC>(G, src, perm, k, l, M, v);
+  spread_visit_v<T, TX, TY, TZ>(G, d, fo, tm, v, l, scale, acc);
 }
 
 // Accumulator unit of a tile: fixed point (single-precision fields) takes
@@ -772,7 +957,7 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
                                   double unit, bool poison, bool overwrite, T *f0, T *f1, T *f2,
                                   uint32_t *status) {
   constexpr bool kFixed = std::is_integral<A_t>::value;
-  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
+  constexpr int PX = AccLayout<TX, TY, TZ>::PX, NODES = AccLayout<TX, TY, TZ>::NODES;
   static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
   constexpr int kRows = 3 * TZ * TY, kStep = kTileThreads / TX;
   constexpr int kPer = (kRows + kStep - 1) / kStep;   // rows per lane
@@ -788,9 +973,7 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
     const int nyc = G.ny + (c == 1 ? 1 : 0);
     if (j >= nyc || k >= G.nz) return false;
     wall = c == 1 && (j == 0 || j == G.ny);
-    a = (acc && !wall) ? acc[c * (PX * PY * PZ) + ((lz + kGuard) * PY + ly + kGuard) * PX + lx +
-                             kGuard]
-                       : (A_t)0;
+    a = (acc && !wall) ? acc[c * NODES + (lz * TY + ly) * PX + lx + kGuard] : (A_t)0;
     if (wall ? !overwrite : (a == (A_t)0 && !poison && !overwrite)) return false;
     g = ((size_t)k * nyc + j) * G.nx + i;
     Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
@@ -833,12 +1016,12 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
 // SRC 0: marker values from the correction buffer dF [3][n*nl] (sorted
 //        spheres); SRC 1: caller-ordered [n][nl][3] values, sphere k of the
 //        sorted order read at perm[k].
-// Waves per SIMD the spreading kernel is compiled for: two 512-thread tiles
-// per compute unit in single precision (the guard-banded accumulators take
-// 57.6 KB of LDS), one in double precision.
+// Waves per SIMD the spreading kernel is compiled for: three 512-thread
+// tiles per compute unit in single precision (about 47 KB of LDS each), two
+// in double precision.
 template <typename T>
 struct TileWaves {
-  static constexpr int value = sizeof(T) == 4 ? 2 * kTileThreads / 256 : kTileThreads / 256;
+  static constexpr int value = (sizeof(T) == 4 ? 3 : 2) * kTileThreads / 256;
 };
 
 template <typename T, int SRC>
@@ -849,10 +1032,9 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     const int *__restrict__ perm, const float *__restrict__ vmax, T *f0, T *f1, T *f2,
     uint32_t *status, TileCache tc) {
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
-  constexpr int PX = TX + 2 * kGuard, PY = TY + 2 * kGuard, PZ = TZ + 2 * kGuard;
-  constexpr int NODES_P = PX * PY * PZ;
+  constexpr int NODES = AccLayout<TX, TY, TZ>::NODES;
   using A_t = typename TileAcc<T>::type;
-  __shared__ A_t acc[3 * NODES_P];
+  __shared__ __attribute__((aligned(16))) A_t acc[3 * NODES];
   __shared__ int c_idx[kTileCand];
   __shared__ int c_l0[kTileCand];
   __shared__ int c_pref[kTileCand + 1];
@@ -907,6 +1089,15 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     }
     const unsigned *reg = tc.items + (size_t)tile * tc.cap;
     const int ncand = tc.ncand[tile];
+    const unsigned *itm = reg + ncand;
+    // the codes of this thread's listed markers (at most kReplayRounds),
+    // loaded with the candidates
+    unsigned code[kReplayRounds];
+#pragma unroll
+    for (int r = 0; r < kReplayRounds; ++r) {
+      const int it = (int)threadIdx.x + r * (int)blockDim.x;
+      code[r] = it < cached ? itm[it] : 0u;
+    }
     for (int t = threadIdx.x; t < ncand; t += blockDim.x) {
       const int k = (int)reg[t];
       c_idx[t] = k;
@@ -923,14 +1114,26 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) vsum += r_wv[w];
     }
     tile_unit<T, kFixed>(G.wsum_bound * dvh * vsum, dvh, unit, poison, scale);
-    for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) acc[q] = (A_t)0;
+    acc_clear<A_t, 3 * NODES>(acc);
     __syncthreads();
-    const unsigned *itm = reg + ncand;
-    for (int it = threadIdx.x; it < cached; it += blockDim.x) {
-      const unsigned cd = itm[it];
-      const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
-      spread_visit<T, SRC, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, src, perm, c_idx[sc], l,
-                                       M, scale, acc);
+    // the listed markers, the next one's values loading while the current
+    // one is accumulated
+    T vc[3] = {(T)0, (T)0, (T)0};
+    if ((int)threadIdx.x < cached)
+      marker_values<T, SRC>(G, src, perm, c_idx[code[0] >> 10], (int)(code[0] & 1023u), M, vc);
+#pragma unroll
+    for (int r = 0; r < kReplayRounds; ++r) {
+      const int it = (int)threadIdx.x + r * (int)blockDim.x;
+      if (it >= cached) break;
+      T vn[3] = {(T)0, (T)0, (T)0};
+      if (r + 1 < kReplayRounds && it + (int)blockDim.x < cached)
+        marker_values<T, SRC>(G, src, perm, c_idx[code[r + 1] >> 10],
+                              (int)(code[r + 1] & 1023u), M, vn);
+      const int sc = (int)(code[r] >> 10);
+      spread_visit_v<T, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, vc,
+                                    (int)(code[r] & 1023u), scale, acc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vc[c] = vn[c];
     }
     __syncthreads();
     tile_flush<T, A_t, TX, TY, TZ>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
@@ -1020,7 +1223,7 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     c_l0[s] = l0;
     c_pref[s] = cnt;
   }
-  for (int q = threadIdx.x; q < 3 * NODES_P; q += blockDim.x) acc[q] = (A_t)0;
+  acc_clear<A_t, 3 * NODES>(acc);
   __syncthreads();
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads): shuffles inside each wave, then the wave

@@ -58,6 +58,10 @@ struct Mech {
   double skin_half2;      // (skin/2)^2
 };
 
+// Entries of a spreading tile's record: candidate sphere indices, then the
+// culled (candidate << 10 | marker) codes; a tile with more is not recorded.
+constexpr int kTileRecord = 2304;
+
 // Scratch owned by a context.
 struct Scratch {
   int cap_n;
@@ -76,7 +80,7 @@ struct Scratch {
   double *ft_part;            // [12][n]: the same for the latest interpolation pass
   double *slip_part;          // [2][n]: slip^2 and zero-forcing slip^2 per sphere
   float *vmax;                // [n]: largest |marker value| per sphere (latest spread source)
-  // per-tile record of the spreading (TileCache)
+  // per-tile record of the spreading (TileCache), kTileRecord entries a tile
   unsigned *tc_items;
   int *tc_count, *tc_ncand;
   int tc_cap;
@@ -149,6 +153,9 @@ hipError_t launch_scan(hipStream_t s, int *data, int n, int *tmp);
 int brick_edge(double R, double h);
 // LDS bytes of one component's interpolation brick (x-rows padded to 16 bytes).
 size_t brick_bytes(int nb, int esz);
+// LDS of the interpolation's brick buffers (one or two bricks)
+int interp_brick_buffers(int nb, int esz);
+size_t interp_lds_bytes(int nb, int esz);
 // Row pitch of the brick in elements: nb rounded up to 16 bytes, plus
 // PRS_BRICK_PAD 16-byte vectors (a knob: padding by one or two vectors
 // measured slower at D/h = 10 on MI355X).
@@ -176,8 +183,8 @@ hipError_t launch_interp_learned(hipStream_t s, const Geom &G, const Scratch &S,
 template <typename T>
 hipError_t launch_accum_target(hipStream_t s, const Geom &G, const Scratch &S, int n, double adt,
                                float *target);
-// Dynamic LDS the learned pass needs besides the grid brick.
-size_t learned_lds_bytes(int nl);
+// Dynamic LDS of the fused learned pass (bricks, network inputs, weights, table).
+size_t learned_lds_bytes(int nl, int nb, int esz);
 // Device buffers of a network (defined with the network).
 void mlp_buffers(const prs_mlp *mlp, LearnArgs *la);
 

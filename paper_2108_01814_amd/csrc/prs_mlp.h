@@ -98,22 +98,24 @@ __device__ inline float gelu(float z) {
   return z * (z >= 0.f ? 1.0f - half_erfc : half_erfc);
 }
 
-// GELU from a table of Phi: quadratic pieces on [-6, 6) with step 1/64,
-// Phi(z_i + f h) = c0 + f (c1 + f c2), f in [0, 1), fitted through Phi at
-// z_i, z_i + h/2 and z_i + h (interpolation error below 2e-7); outside
-// [-6, 6] Phi is within 1e-9 of 0 or 1 and the end pieces are used.  Eight
-// vector operations and one LDS read instead of the erfcc fit's exponential
-// and reciprocal: the fused learned pass evaluates 128 GELUs per marker.
-constexpr int kGeluTabN = 768;
-constexpr float kGeluZ0 = -6.0f, kGeluInvStep = 64.0f;
+// GELU from a table of Phi: cubic pieces on [-6, 6) with step 1/16,
+// Phi(z_i + f h) = c0 + f (c1 + f (c2 + f c3)), f in [0, 1), through Phi at
+// z_i + {0, 1/3, 2/3, 1} h (interpolation error below 5e-9: h^4 / 24 times
+// the largest fourth derivative of Phi, < 0.55, times the largest
+// |f (f - 1/3) (f - 2/3) (f - 1)|, < 0.0124); outside [-6, 6] Phi is within
+// 1e-9 of 0 or 1 and the end pieces are used.  Nine vector operations and one
+// LDS read instead of the erfcc fit's exponential and reciprocal: the fused
+// learned pass evaluates 128 GELUs per marker.
+constexpr int kGeluTabN = 192;
+constexpr float kGeluZ0 = -6.0f, kGeluInvStep = 16.0f;
 
 __device__ inline float gelu_tab(const float4 *tab, float z) {
   const float u = fminf(fmaxf(fmaf(z, kGeluInvStep, -kGeluZ0 * kGeluInvStep), 0.0f),
                         (float)kGeluTabN - 0.001f);
-  const float fi = floorf(u);
-  const float f = u - fi;
-  const float4 c = tab[(int)fi];
-  return z * fmaf(f, fmaf(f, c.z, c.y), c.x);
+  // u >= 0: the piece is the truncation, f its exact fractional part
+  const float f = __builtin_amdgcn_fractf(u);
+  const float4 c = tab[(int)u];
+  return z * fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
 }
 
 // The activation of the forward pass: the erfcc fit, or the table.
@@ -150,21 +152,25 @@ __device__ inline bf16x4 lds4(const unsigned short *p) {
 //   g2[t][kc][lane] = W2[16kc + 4q + j][16t + r], j = 0..3   (W2^T, backward)
 //   g3[t][lane]     = W3[4q + j][16t + r], j = 0..3          (W3^T, backward)
 // plus the FP32 biases.
-struct alignas(16) MlpLds {
+// The forward pass's part (the fused learned pass stages only this).
+struct alignas(16) MlpFwdLds {
   bf16x4 f1[4][64];
   bf16x4 f2[4][4][64];
   bf16x4 f3[4][64];
+  float b1[kMlpHid], b2[kMlpHid], b3[kMlpOut];
+};
+struct alignas(16) MlpLds : MlpFwdLds {
   bf16x4 g2[4][4][64];
   bf16x4 g3[4][64];
-  float b1[kMlpHid], b2[kMlpHid], b3[kMlpOut];
 };
 
 constexpr size_t kMlpLdsBytes = (sizeof(MlpLds) + 15) & ~(size_t)15;
+constexpr size_t kMlpFwdLdsBytes = (sizeof(MlpFwdLds) + 15) & ~(size_t)15;
 
-// Whole workgroup: stage the BF16 weights as fragments and the FP32 biases
-// (transposed: also the W2^T and W3^T fragments of the backward pass).
-__device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ wbf,
-                                 const float *__restrict__ master, bool transposed) {
+// Whole workgroup: stage the forward pass's BF16 weight fragments and FP32
+// biases.
+__device__ inline void mlp_stage_fwd(MlpFwdLds &L, const unsigned short *__restrict__ wbf,
+                                     const float *__restrict__ master) {
   auto frag = [&](int off) { return *reinterpret_cast<const bf16x4 *>(wbf + off); };
   for (int e = threadIdx.x; e < 4 * 64; e += blockDim.x) {
     const int t = e >> 6, lane = e & 63, r = lane & 15, q = lane >> 4;
@@ -175,6 +181,18 @@ __device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ w
     const int t = e >> 8, kc = (e >> 6) & 3, lane = e & 63, r = lane & 15, q = lane >> 4;
     L.f2[t][kc][lane] = frag(kOffW2 + (16 * t + r) * kMlpHid + 16 * kc + 4 * q);
   }
+  for (int i = threadIdx.x; i < kMlpHid; i += blockDim.x) {
+    L.b1[i] = master[kOffB1 + i];
+    L.b2[i] = master[kOffB2 + i];
+  }
+  for (int i = threadIdx.x; i < kMlpOut; i += blockDim.x) L.b3[i] = master[kOffB3 + i];
+}
+
+// Whole workgroup: the forward part, and with transposed also the W2^T and
+// W3^T fragments of the backward pass.
+__device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ wbf,
+                                 const float *__restrict__ master, bool transposed) {
+  mlp_stage_fwd(L, wbf, master);
   if (transposed) {
     for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
       const int t = e >> 8, kc = (e >> 6) & 3, lane = e & 63, r = lane & 15, q = lane >> 4;
@@ -190,11 +208,6 @@ __device__ inline void mlp_stage(MlpLds &L, const unsigned short *__restrict__ w
       L.g3[t][lane] = v;
     }
   }
-  for (int i = threadIdx.x; i < kMlpHid; i += blockDim.x) {
-    L.b1[i] = master[kOffB1 + i];
-    L.b2[i] = master[kOffB2 + i];
-  }
-  for (int i = threadIdx.x; i < kMlpOut; i += blockDim.x) L.b3[i] = master[kOffB3 + i];
 }
 
 // Activations of one 16-marker tile in the C/B lane layout: lane (q = l/16,
@@ -207,7 +220,7 @@ struct MlpFwd {
 // Forward pass of one tile.  xb: B operand of the standardised input, lane
 // (q, r) holding features 4q..4q+3 of marker r.  act: the GELU evaluation.
 template <class Act = GeluFit>
-__device__ inline void mlp_forward_tile(const MlpLds &L, bf16x4 xb, MlpFwd &s, Act act = Act{}) {
+__device__ inline void mlp_forward_tile(const MlpFwdLds &L, bf16x4 xb, MlpFwd &s, Act act = Act{}) {
   const int lane = threadIdx.x & 63, q = lane >> 4;
   s.xb = xb;
 #pragma unroll

@@ -201,16 +201,18 @@ __global__ void k_mlp_adam(float *master, float *m, float *v, const float *__res
 }
 
 // Table of the GELU of the fused learned pass (gelu_tab): piece i on
-// [z_i, z_i + h], z_i = -6 + i h, h = 1/64, the quadratic through Phi at its
-// ends and midpoint, Phi(z) = erfc(-z / sqrt 2) / 2 in double precision.
+// [z_i, z_i + h], z_i = -6 + i h, h = 1/16, the cubic through Phi at
+// z_i + {0, 1/3, 2/3, 1} h (Newton's forward differences written in powers
+// of f), Phi(z) = erfc(-z / sqrt 2) / 2 in double precision.
 __global__ void k_gelu_table(float4 *tab) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kGeluTabN) return;
   const double h = 1.0 / (double)kGeluInvStep, z = (double)kGeluZ0 + i * h;
   auto Phi = [](double v) { return 0.5 * erfc(-v * 0.70710678118654752440); };
-  const double p0 = Phi(z), pm = Phi(z + 0.5 * h), p1 = Phi(z + h);
-  const double c2 = 2.0 * (p0 + p1 - 2.0 * pm), c1 = p1 - p0 - c2;
-  tab[i] = make_float4((float)p0, (float)c1, (float)c2, 0.f);
+  const double p0 = Phi(z), p1 = Phi(z + h / 3.0), p2 = Phi(z + 2.0 * h / 3.0), p3 = Phi(z + h);
+  const double d1 = p1 - p0, d2 = p2 - 2.0 * p1 + p0, d3 = p3 - 3.0 * p2 + 3.0 * p1 - p0;
+  tab[i] = make_float4((float)p0, (float)(3.0 * d1 - 1.5 * d2 + d3), (float)(4.5 * (d2 - d3)),
+                       (float)(4.5 * d3));
 }
 
 __global__ void k_mlp_round(const float *__restrict__ master, unsigned short *wbf) {

@@ -39,6 +39,13 @@ __device__ inline void sphere_axis(double x, double inv_h, int &I, T fo[2]) {
   fo[1] = phi - (T)0.5;
 }
 
+// Square root of the kernel's 1 - 3 r^2 (in [1/4, 1]): the hardware
+// instruction in single precision (within about one unit in the last place;
+// the correctly rounded library form costs a dozen more instructions per
+// stencil), the correctly rounded one in double precision.
+__device__ inline float kernel_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double kernel_sqrt(double x) { return sqrt(x); }
+
 // Stencil along one axis: centre offset c (nodes I + c - 1 .. I + c + 1)
 // and the three weights.  Written with explicit fused operations so that
 // every inlined copy rounds identically.
@@ -46,7 +53,7 @@ template <typename T>
 __device__ inline int stencil_axis(T fo, T mhi, T mlo, T w[3]) {
   const T cf = floor((fo + mhi) + (T)0.5);
   const T r = ((mhi - cf) + fo) + mlo;
-  const T q = sqrt(fma((T)-3 * r, r, (T)1));
+  const T q = kernel_sqrt(fma((T)-3 * r, r, (T)1));
   const T a = (T)2 - q;
   w[0] = fma((T)-3, r, a) * (T)(1.0 / 6.0);
   w[1] = fma(q, (T)(1.0 / 3.0), (T)(1.0 / 3.0));

@@ -2,9 +2,9 @@
 
 - Training samples (features and plain-forcing targets) against the oracle.
 - The fused network pass: with a network whose output does not depend on its
-  inputs (zero weights, bias only) both sides form the same F0 exactly, so the
-  learned step must match the oracle step started from that F0 to the usual
-  parity bounds (FP64 1e-11, FP32 1e-5).
+  inputs (zero weights, bias only) both sides form the same F0 (to an FP64
+  rounding), so the learned step must match the oracle step started from
+  that F0 to the usual parity bounds (FP64 1e-11, FP32 1e-5).
 - With a realistic network the BF16 roundings of the device (FP32
   accumulation) and of the oracle (FP64 accumulation) can fall on different
   sides of a tie for a few activations; the initial force then agrees per
