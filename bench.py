@@ -424,7 +424,7 @@ def roofline_block(w, r, s, K, copy_gbs, tname):
     nb = 2 * math.ceil(0.5 * W.PHYS["D"] / w.h - 1e-9) + 4
     kern = {f"prs::k_interp<{tname}, 0, {nb}>": ("interpolation", b_interp, avg_interp,
                                                  tm["ms_interp"]),
-            f"prs::k_spread_tiles<{tname}, 0>": ("spreading", b_spread, avg_spread,
+            f"prs::k_spread_tiles<{tname}, 0, false>": ("spreading", b_spread, avg_spread,
                                                  tm["ms_spread"])}
     dom = max(kern, key=lambda k: kern[k][3])
     _, bts, ms, _ = kern[dom]

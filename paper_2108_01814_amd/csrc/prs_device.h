@@ -46,22 +46,31 @@ enum : int {
   kDppBcast31 = 0x143,      // lane 31 -> rows 2 and 3
 };
 
+// One 32-bit word: with every row written (ROW_MASK 0xF) the plain move,
+// else the update with 0 for the lanes of the rows left out.
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_word(int v) {
+  if constexpr (ROW_MASK == 0xF)
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+  else
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  const int lo = dpp_word<CTRL, ROW_MASK>(__double2loint(v));
+  const int hi = dpp_word<CTRL, ROW_MASK>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
 
 template <int CTRL, int ROW_MASK>
 __device__ inline float dpp_move(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+  return __int_as_float(dpp_word<CTRL, ROW_MASK>(__float_as_int(v)));
 }
 
 template <int CTRL, int ROW_MASK>
 __device__ inline int dpp_move(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+  return dpp_word<CTRL, ROW_MASK>(v);
 }
 
 // Sum over the wave, valid in lane 63: butterflies inside each quad, mirrors

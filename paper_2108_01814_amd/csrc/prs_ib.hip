@@ -179,6 +179,11 @@ __device__ inline void lds_load16(const void *src, void *wave_base) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)wave_base, 16,
                                    0, 0);
 }
+// 4 bytes per lane the same way: lane i writes at wave_base + 4 i.
+__device__ inline void lds_load4(const void *src, void *wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)wave_base, 4,
+                                   0, 0);
+}
 // Waits until this wave's memory operations have completed.
 __device__ inline void wait_loads() { __builtin_amdgcn_s_waitcnt(0); }
 
@@ -223,6 +228,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     }
   }
   const T tadt = (T)adt;
+  const T inv_tadt = (T)(1.0 / adt);   // the correction r / (alpha dt) by multiplication
   // An MDF pass over a nonzero f interpolates f alone and adds the step's
   // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
   // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
@@ -302,6 +308,13 @@ __global__ __launch_bounds__(1024) void k_interp(
     }
   };
   T U[3] = {(T)0, (T)0, (T)0};
+  // Single-precision MDF passes over f read the recorded I[u-hat] through
+  // LDS (loaded while the last stencils run) when the bricks are double
+  // buffered.
+  constexpr bool kU0Lds = sizeof(T) == 4 && MODE == kInterpMDF && PRS_INTERP_DMA != 0;
+  const bool u0_in_lds =
+      kU0Lds && f_only && u0 != nullptr && nbuf == 2 && per_comp <= kSlots * bdim;
+  T u0_val[3] = {(T)0, (T)0, (T)0};
   // the field of component c that this pass interpolates
   auto field = [&](int c) {
     return f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
@@ -394,12 +407,27 @@ __global__ __launch_bounds__(1024) void k_interp(
     for (int c = 0; c < 3; ++c) {
       // buf[(c + 1) & 1] was last read by component c - 1, before the
       // barrier that ended the previous round
-      if (c < 2) dma_component(c + 1, buf[(c + 1) & 1]);
+      if (c < 2) {
+        dma_component(c + 1, buf[(c + 1) & 1]);
+      } else if (kU0Lds && u0_in_lds) {
+        // the recorded I[u-hat] of this lane's marker, into the free buffer
+        // while the last component's stencils run
+        const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
+        if (active)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            lds_load4(u0 + cc * M + m, buf[1] + cc * bdim + wave_base);
+      }
       stencil_component(c, buf[c & 1]);
       if (c < 2) {
         wait_loads();
         __syncthreads();
       }
+    }
+    if (kU0Lds && u0_in_lds) {
+      wait_loads();   // each lane reads the values its own wave loaded
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) u0_val[cc] = buf[1][cc * bdim + (int)threadIdx.x];
     }
   } else {
     vec_t nxt[kSlots];
@@ -456,16 +484,26 @@ __global__ __launch_bounds__(1024) void k_interp(
       wp[a] = ws[a * N + p];
     }
   }
+  // the lever arm R t_l: in single precision from the marker offset in node
+  // units already in registers, h (m_hi + m_lo), within a few FP64
+  // roundings of R t_l (double precision, and the modes with the normal
+  // among their features, read the template)
   double rl[3] = {0, 0, 0};
-  if (active)
-    for (int a = 0; a < 3; ++a) rl[a] = G.R * templ[3 * l + a];
+  if (active) {
+    if (sizeof(T) == 8 || MODE == kInterpFeat || MODE == kInterpLearned)
+      for (int a = 0; a < 3; ++a) rl[a] = G.R * templ[3 * l + a];
+    else
+      for (int a = 0; a < 3; ++a) rl[a] = G.h * ((double)mhi[a] + (double)mlo[a]);
+  }
   const double Ud[3] = {up[0] + (wp[1] * rl[2] - wp[2] * rl[1]),
                         up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
 
   if (MODE != kInterpPlain && active && u0) {
     const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
-    if (f_only)
+    if (kU0Lds && u0_in_lds)
+      for (int c = 0; c < 3; ++c) U[c] = u0_val[c] + tadt * U[c];
+    else if (f_only)
       for (int c = 0; c < 3; ++c) U[c] = u0[c * M + m] + tadt * U[c];
     else
       for (int c = 0; c < 3; ++c) u0[c * M + m] = U[c];
@@ -554,7 +592,7 @@ __global__ __launch_bounds__(1024) void k_interp(
       double d[3];
       for (int c = 0; c < 3; ++c) {
         const T res = (T)Ud[c] - U[c];
-        const T corr = res / tadt;
+        const T corr = res * inv_tadt;
         out[c * M + m] = corr;
         vm = nan_max(vm, fabsf((float)corr));
         d[c] = (double)corr;
@@ -961,21 +999,33 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
   static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
   constexpr int kRows = 3 * TZ * TY, kStep = kTileThreads / TX;
   constexpr int kPer = (kRows + kStep - 1) / kStep;   // rows per lane
+  static_assert((TZ * TY) % kStep == 0 && kStep % TY == 0,
+                "a round of rows stays within one component and starts a plane");
+  // Row q of this lane: component c = q kStep / (TZ TY) and plane
+  // lz0 + dz(q) are the same for every lane of the round, the y-row ly and
+  // the first plane lz0 are the lane's own; so each row's field index is the
+  // lane's base for its component plus a uniform multiple of the plane size.
   const int lx = threadIdx.x & (TX - 1), i = i0 + lx;
-  // the lane's q-th row: its node's field, index and sum; false where the
-  // row has nothing to write
+  const int r0 = threadIdx.x / TX, ly = r0 % TY, lz0 = r0 / TY;
+  const int j = j0 + ly;
+  const bool lane_ok = i < G.nx;
+  const size_t base_uw = ((size_t)(k0 + lz0) * G.ny + j) * G.nx + i;
+  const size_t base_v = ((size_t)(k0 + lz0) * (G.ny + 1) + j) * G.nx + i;
+  auto row_of = [&](int q, int &c, int &dz) {
+    c = (q * kStep) / (TZ * TY);
+    dz = ((q * kStep) % (TZ * TY)) / TY;
+  };
+  // the lane's q-th row: false where it has nothing to write
   auto node = [&](int q, T *&Fp, size_t &g, A_t &a, bool &wall) {
-    const int row = threadIdx.x / TX + q * kStep;
-    if (row >= kRows || i >= G.nx) return false;
-    const int c = row / (TZ * TY), rz = row - c * (TZ * TY);
-    const int lz = rz / TY, ly = rz - lz * TY;
-    const int j = j0 + ly, k = k0 + lz;
+    int c, dz;
+    row_of(q, c, dz);
     const int nyc = G.ny + (c == 1 ? 1 : 0);
-    if (j >= nyc || k >= G.nz) return false;
+    const int lz = lz0 + dz;
+    if (!lane_ok || j >= nyc || k0 + lz >= G.nz) return false;
     wall = c == 1 && (j == 0 || j == G.ny);
     a = (acc && !wall) ? acc[c * NODES + (lz * TY + ly) * PX + lx + kGuard] : (A_t)0;
     if (wall ? !overwrite : (a == (A_t)0 && !poison && !overwrite)) return false;
-    g = ((size_t)k * nyc + j) * G.nx + i;
+    g = (c == 1 ? base_v : base_uw) + (size_t)dz * ((size_t)nyc * (size_t)G.nx);
     Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
     return true;
   };
@@ -1023,10 +1073,19 @@ template <typename T>
 struct TileWaves {
   static constexpr int value = (sizeof(T) == 4 ? 3 : 2) * kTileThreads / 256;
 };
+// The record-only form (no accumulators, 7 KB of LDS): 256-thread tiles,
+// eight per compute unit (its code uses blockDim, and needs at least
+// kTileCand threads for the scan and kTileList >= 2 blockDim).
+constexpr int kRecordThreads = 256;
+constexpr int kRecordWaves = 8 * kRecordThreads / 256;
+static_assert(kRecordThreads >= kTileCand && kTileList >= 2 * kRecordThreads, "record-only tiles");
 
-template <typename T, int SRC>
+// kRecordOnly: only the first part, each tile's candidates and culled
+// markers recorded for the spreading passes that follow (no accumulators,
+// so many more tiles fit a compute unit; f untouched).
+template <typename T, int SRC, bool kRecordOnly = false>
 __global__ __launch_bounds__(kTileThreads)
-__attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
+__attribute__((amdgpu_waves_per_eu(kRecordOnly ? kRecordWaves : TileWaves<T>::value))) void k_spread_tiles(
     Geom G, Cells C, const int *__restrict__ start, const double *__restrict__ xs, int n,
     const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ src,
     const int *__restrict__ perm, const float *__restrict__ vmax, T *f0, T *f1, T *f2,
@@ -1034,11 +1093,11 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   constexpr int TX = TileShape<T>::X, TY = TileShape<T>::Y, TZ = TileShape<T>::Z;
   constexpr int NODES = AccLayout<TX, TY, TZ>::NODES;
   using A_t = typename TileAcc<T>::type;
-  __shared__ __attribute__((aligned(16))) A_t acc[3 * NODES];
+  __shared__ __attribute__((aligned(16))) A_t acc[kRecordOnly ? 4 : 3 * NODES];
   __shared__ int c_idx[kTileCand];
   __shared__ int c_l0[kTileCand];
   __shared__ int c_pref[kTileCand + 1];
-  __shared__ TileCand<T> c_geo[kTileCand];
+  __shared__ TileCand<T> c_geo[kRecordOnly ? 1 : kTileCand];
   __shared__ int c_n;
   __shared__ unsigned c_list[kTileList];   // culled (candidate << 10 | marker)
   __shared__ int c_list_n;
@@ -1079,8 +1138,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
 
   // Replay: this step's earlier pass recorded the tile's candidates and
   // culled markers (the spheres have not moved since).
-  const int cached = tc.mode == 2 ? tc.count[tile] : -1;   // uniform
-  if (cached >= 0) {
+  const int cached = (!kRecordOnly && tc.mode == 2) ? tc.count[tile] : -1;   // uniform
+  if (!kRecordOnly && cached >= 0) {
     if (cached == 0) {
       if (tc.overwrite)
         tile_flush<T, A_t, TX, TY, TZ>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
@@ -1169,7 +1228,8 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
         const int slot = atomicAdd(&c_n, 1);
         if (slot < kTileCand) {
           c_idx[slot] = k;
-          tile_cand<T, TX, TY, TZ>(G, px, py, pz, i0, j0, k0, c_geo[slot].d, c_geo[slot].fo);
+          if constexpr (!kRecordOnly)
+            tile_cand<T, TX, TY, TZ>(G, px, py, pz, i0, j0, k0, c_geo[slot].d, c_geo[slot].fo);
         }
       }
     }
@@ -1179,7 +1239,7 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
   const bool record = tc.mode == 1;
   if (nc == 0) {
     if (record && threadIdx.x == 0) tc.count[tile] = 0;
-    if (tc.overwrite)
+    if (!kRecordOnly && tc.overwrite)
       tile_flush<T, A_t, TX, TY, TZ>(G, nullptr, i0, j0, k0, 1.0, false, true, f0, f1, f2,
                                      status);
     return;
@@ -1223,7 +1283,7 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     c_l0[s] = l0;
     c_pref[s] = cnt;
   }
-  acc_clear<A_t, 3 * NODES>(acc);
+  if constexpr (!kRecordOnly) acc_clear<A_t, 3 * NODES>(acc);
   __syncthreads();
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads): shuffles inside each wave, then the wave
@@ -1239,13 +1299,13 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
       if (ln >= off) incl += y;
     }
     if (t < kTileCand && ln == 63) c_wsum[t >> 6] = incl;
-    if (kFixed) {
+    if (kFixed && !kRecordOnly) {
       double vs = t < nc ? (double)vmax[c_idx[t]] : 0.0;
       vs = wave_sum_last(vs);
       if (t < kTileCand && ln == 63) c_wvsum[t >> 6] = vs;
     }
     __syncthreads();
-    if (kFixed)
+    if (kFixed && !kRecordOnly)
       for (int w = 0; w < kTileCand / 64; ++w) vsum += c_wvsum[w];
     if (t < kTileCand) {
       int base = 0;
@@ -1274,11 +1334,11 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
         if (c_pref[mid] <= item) a = mid; else b = mid;
       }
       const int l = c_l0[a] + (item - c_pref[a]);
+      // a marker outside the tile's reach box touches none of its nodes
+      // (conservative; the exact test is each component's stencil range)
       const int k = c_idx[a];
       const double X0 = xs[k] + R * templ[3 * l], X1 = xs[N + k] + R * templ[3 * l + 1],
                    X2 = xs[2 * N + k] + R * templ[3 * l + 2];
-      // a marker outside the tile's reach box touches none of its nodes
-      // (conservative; the exact test is each component's stencil range)
       pass = fabs(min_image(X0 - mctr[0], G.Lx)) <= mhw[0] && fabs(X1 - mctr[1]) <= mhw[1] &&
              fabs(min_image(X2 - mctr[2], G.Lz)) <= mhw[2];
       code = ((unsigned)a << 10) | (unsigned)l;
@@ -1299,8 +1359,9 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
         const unsigned cd = c_list[it];
         const int sc = (int)(cd >> 10), l = (int)(cd & 1023u);
         if (keep) reg[rbase + it] = cd;
-        spread_visit<T, SRC, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, src, perm, c_idx[sc],
-                                         l, M, scale, acc);
+        if constexpr (!kRecordOnly)
+          spread_visit<T, SRC, TX, TY, TZ>(G, c_geo[sc].d, c_geo[sc].fo, tm, src, perm,
+                                           c_idx[sc], l, M, scale, acc);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1314,6 +1375,7 @@ __attribute__((amdgpu_waves_per_eu(TileWaves<T>::value))) void k_spread_tiles(
     tc.count[tile] = r_len >= 0 ? r_len - nc : -1;
     tc.ncand[tile] = nc;
   }
+  if constexpr (kRecordOnly) return;
   __syncthreads();
   tile_flush<T, A_t, TX, TY, TZ>(G, acc, i0, j0, k0, unit, poison, tc.overwrite, f0, f1, f2,
                                  status);
@@ -1362,6 +1424,15 @@ hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, con
   if (n == 0) return hipSuccess;
   const int ntiles = spread_tile_count<T>(G);
   if (!tc.items) tc.mode = 0;
+  if (tc.mode == 1) {
+    // the records first, by the record-only form (more tiles resident), then
+    // this pass replays them like the later ones
+    hipLaunchKernelGGL((k_spread_tiles<T, 0, true>), dim3(xcd_grid(ntiles)), dim3(kRecordThreads),
+                       0, s, G, C, S.start, S.xs[0], n, S.templ,
+                       (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64),
+                       (const T *)S.dF, S.perm, S.vmax, f[0], f[1], f[2], S.status, tc);
+    tc.mode = 2;
+  }
   const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
   // caller values: their per-sphere maxima first (the correction buffer's are
   // written by the interpolation pass that fills it)

@@ -175,7 +175,9 @@ __global__ void k_gather_state(const int *__restrict__ perm, int n, Geom G,
     c = c < 0 ? 0 : kSlots;
   }
   h_cnt[j] = c;
+  // only the slots in use (the substeps read no slot at or past the count)
   for (int sl = 0; sl < kSlots; ++sl) {
+    if (sl >= c) break;
     h_id[sl * (size_t)n + j] = hp[(size_t)i * kSlots + sl];
     h_uin[sl * (size_t)n + j] = hu[(size_t)i * kSlots + sl];
     for (int a = 0; a < 3; ++a)
@@ -235,7 +237,7 @@ __global__ void k_writeback(const int *__restrict__ perm, int n, const uint32_t 
                             const int *__restrict__ h_id, const double *__restrict__ h_dt,
                             const double *__restrict__ h_uin, double *x, double *u, double *om,
                             double *Fh, double *Th, int32_t *hp, double *hd, double *hu,
-                            int8_t *hc) {
+                            int8_t *hc, int vec) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int i = perm[j];
@@ -251,22 +253,46 @@ __global__ void k_writeback(const int *__restrict__ perm, int n, const uint32_t 
   }
   const int c = h_cnt[j];
   hc[i] = (int8_t)c;
-  for (int sl = 0; sl < kSlots; ++sl) {
-    const bool has = sl < c;
-    hp[(size_t)i * kSlots + sl] = has ? h_id[sl * (size_t)n + j] : 0;
-    hu[(size_t)i * kSlots + sl] = has ? h_uin[sl * (size_t)n + j] : 0.0;
-    for (int a = 0; a < 3; ++a)
-      hd[((size_t)i * kSlots + sl) * 3 + a] = has ? h_dt[(sl * 3 + a) * (size_t)n + j] : 0.0;
+  // the caller's rows, two slots per round with 8- and 16-byte stores when
+  // the arrays allow (zeros past the count); the sorted slots read only
+  // where in use
+  static_assert(kSlots % 2 == 0, "slot pairs");
+  for (int sl = 0; sl < kSlots; sl += 2) {
+    int id[2] = {0, 0};
+    double ui[2] = {0.0, 0.0}, dt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < 2; ++e)
+      if (sl + e < c) {
+        id[e] = h_id[(sl + e) * (size_t)n + j];
+        ui[e] = h_uin[(sl + e) * (size_t)n + j];
+        for (int a = 0; a < 3; ++a) dt[3 * e + a] = h_dt[((sl + e) * 3 + a) * (size_t)n + j];
+      }
+    const size_t r = (size_t)i * kSlots + sl;
+    if (vec) {
+      *reinterpret_cast<int2 *>(hp + r) = make_int2(id[0], id[1]);
+      *reinterpret_cast<double2 *>(hu + r) = make_double2(ui[0], ui[1]);
+      for (int q = 0; q < 3; ++q)
+        reinterpret_cast<double2 *>(hd + 3 * r)[q] = make_double2(dt[2 * q], dt[2 * q + 1]);
+    } else {
+      for (int e = 0; e < 2; ++e) {
+        hp[r + e] = id[e];
+        hu[r + e] = ui[e];
+      }
+      for (int q = 0; q < 6; ++q) hd[3 * r + q] = dt[q];
+    }
   }
 }
 
 hipError_t launch_writeback(hipStream_t s, const Scratch &S, double *x, double *u, double *om,
                             const prs_history *H, double *Fh, double *Th, int n, int buf) {
   if (n == 0) return hipSuccess;
+  // slot pairs of a row start at multiples of 8 (partners) and 16 bytes
+  // (u_in, delta_t) when the arrays themselves are 16-byte aligned
+  const int vec = ((reinterpret_cast<uintptr_t>(H->partner) | reinterpret_cast<uintptr_t>(H->delta_t) |
+                    reinterpret_cast<uintptr_t>(H->u_in)) & 15u) == 0;
   hipLaunchKernelGGL(k_writeback, dim3((n + 255) / 256), dim3(256), 0, s, S.perm, n, S.status,
                      S.xs[buf], S.us[buf], S.ws[buf], S.fh, S.th, S.h_cnt[buf], S.h_id[buf],
                      S.h_dt[buf], S.h_uin[buf], x, u, om, Fh, Th, H->partner, H->delta_t, H->u_in,
-                     H->count);
+                     H->count, vec);
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ namespace prs {
 //     (m_hi - c is exact or nearly so, and |r| <= 1/2);
 //   - the three-point kernel (regularised delta function) at the nodes
 //     I + c - 1, I + c, I + c + 1: with q = sqrt(1 - 3 r^2),
-//     w(c) = (1 + q) / 3, w(c -+ 1) = (2 -+ 3 r - q) / 6.
+//     w(c) = (1 + q) / 3, w(c -+ 1) = (2 -+ 3 r - q) / 6, evaluated as
+//     (2 - q) / 6 -+ r / 2.
 // Near r = +-1/2 the floor may pick either neighbour; both choices give the
 // same weights on the same nodes (w = 0, 1/2, 1/2 and 1/2, 1/2, 0), so the
 // stencil is continuous there.
@@ -54,10 +55,10 @@ __device__ inline int stencil_axis(T fo, T mhi, T mlo, T w[3]) {
   const T cf = floor((fo + mhi) + (T)0.5);
   const T r = ((mhi - cf) + fo) + mlo;
   const T q = kernel_sqrt(fma((T)-3 * r, r, (T)1));
-  const T a = (T)2 - q;
-  w[0] = fma((T)-3, r, a) * (T)(1.0 / 6.0);
+  const T a6 = fma(q, (T)(-1.0 / 6.0), (T)(1.0 / 3.0));   // (2 - q) / 6
+  w[0] = fma((T)-0.5, r, a6);
   w[1] = fma(q, (T)(1.0 / 3.0), (T)(1.0 / 3.0));
-  w[2] = fma((T)3, r, a) * (T)(1.0 / 6.0);
+  w[2] = fma((T)0.5, r, a6);
   return (int)cf;
 }
 
