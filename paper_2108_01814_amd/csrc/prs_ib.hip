@@ -124,8 +124,10 @@ __host__ __device__ inline size_t learned_io_region(int block, size_t bricks) {
   return bricks > io ? bricks : io;
 }
 
+// (one brick buffer: the network's LDS and its occupancy matter more here
+// than overlapping the brick loads)
 size_t learned_lds_bytes(int nl, int nb, int esz) {
-  return learned_io_region(block_for(nl), interp_lds_bytes(nb, esz)) + kMlpFwdLdsBytes +
+  return learned_io_region(block_for(nl), brick_bytes(nb, esz)) + kMlpFwdLdsBytes +
          kGeluTabN * sizeof(float4);
 }
 
@@ -642,7 +644,7 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const Scratch &S, con
   if (n == 0) return hipSuccess;
   const int nb = brick_edge(G.R, G.h);
   const dim3 grid(xcd_grid(n)), block(block_for(G.nl));
-  const int nbuf = interp_brick_buffers(nb, sizeof(T));
+  const int nbuf = MODE == kInterpLearned ? 1 : interp_brick_buffers(nb, sizeof(T));
   size_t lds = brick_bytes(nb, sizeof(T)) * nbuf;
   if (MODE == kInterpLearned) lds = learned_lds_bytes(G.nl, nb, sizeof(T));
   const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
