@@ -282,6 +282,9 @@ typedef struct prs_timing {
     int64_t n_interp, n_spread, n_substep;
     double ms_learned;     /* the fused feature + network pass of a learned start */
     int64_t n_learned;
+    double ms_record;      /* the spreading tiles' records (once per step, before the
+                              first spreading pass) */
+    int64_t n_record;
 } prs_timing;
 
 /* ---- learned warm start ------------------------------------------------

@@ -96,7 +96,8 @@ class Timing(C.Structure):
                 ("ms_interp", C.c_double), ("ms_spread", C.c_double), ("ms_search", C.c_double),
                 ("ms_substep", C.c_double), ("ms_writeback", C.c_double),
                 ("n_interp", C.c_int64), ("n_spread", C.c_int64), ("n_substep", C.c_int64),
-                ("ms_learned", C.c_double), ("n_learned", C.c_int64)]
+                ("ms_learned", C.c_double), ("n_learned", C.c_int64),
+                ("ms_record", C.c_double), ("n_record", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

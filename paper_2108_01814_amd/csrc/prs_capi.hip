@@ -13,6 +13,10 @@
 
 using namespace prs;
 
+// Phases of the step timed by prs_timing_* (one slot each).
+enum Phase { kZeroF = 0, kSort, kInterp, kSpread, kSearch, kSubstep, kWriteback, kLearned, kRecord };
+constexpr int kPhases = 9;
+
 struct prs_ctx {
   prs_params p{};
   Geom G{};
@@ -33,8 +37,8 @@ struct prs_ctx {
   };
   std::vector<Mark> marks;
   hipEvent_t open_ev = nullptr;
-  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[kPhases] = {};
+  int64_t launches[kPhases] = {};
   const prs_mlp *mlp = nullptr;   // learned warm start (prs_set_learned)
   int64_t steps = 0;
 };
@@ -123,8 +127,6 @@ int check_n(prs_ctx *c, int32_t n) {
   return PRS_OK;
 }
 
-enum Phase { kZeroF = 0, kSort, kInterp, kSpread, kSearch, kSubstep, kWriteback, kLearned };
-constexpr int kPhases = 8;
 
 hipError_t next_event(prs_ctx *c, hipEvent_t *ev) {
   if (c->events_used == c->events.size()) {
@@ -201,10 +203,19 @@ int run_forcing(prs_ctx *c, hipStream_t s, double adt, const void *const uhat[3]
   // pass, which overwrites every node instead of adding
   bool pending_clear = clear_f;
   auto tile_cache = [&]() {
-    TileCache tc{spreads++ == 0 ? 1 : 2, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
+    TileCache tc{2, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
     tc.overwrite = pending_clear ? 1 : 0;
     pending_clear = false;
     return tc;
+  };
+  // the tiles' records, before the step's first spreading pass (a phase of
+  // its own)
+  auto record_tiles = [&]() -> hipError_t {
+    if (spreads++ > 0) return hipSuccess;
+    hipError_t e = phase_begin(c, s);
+    if (e == hipSuccess) e = launch_tile_record<T>(s, c->G, c->C_step, S, n);
+    if (e == hipSuccess) e = phase_end(c, s, kRecord);
+    return e;
   };
   if (learned) {
     // features, zero-forcing slip and the prediction F0 -> dF in one pass
@@ -216,6 +227,7 @@ int run_forcing(prs_ctx *c, hipStream_t s, double adt, const void *const uhat[3]
     HIP_TRY(c, launch_slip_reduce(s, S, n, 0, 1));
     HIP_TRY(c, launch_ib_begin(s, S, n));
     HIP_TRY(c, launch_ft_commit(s, S, n));
+    HIP_TRY(c, record_tiles());
     HIP_TRY(c, phase_begin(c, s));
     HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr, tile_cache()));
     HIP_TRY(c, phase_end(c, s, kSpread));
@@ -230,6 +242,7 @@ int run_forcing(prs_ctx *c, hipStream_t s, double adt, const void *const uhat[3]
     }
     if (F0) {
       HIP_TRY(c, launch_marker_sums<T>(s, c->G, S, n, (const T *)F0));
+      HIP_TRY(c, record_tiles());
       HIP_TRY(c, phase_begin(c, s));
       HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, (const T *)F0,
                                         tile_cache()));
@@ -278,6 +291,7 @@ int run_forcing(prs_ctx *c, hipStream_t s, double adt, const void *const uhat[3]
     }
     if (target) HIP_TRY(c, launch_accum_target<T>(s, c->G, S, n, adt, target));
     HIP_TRY(c, launch_ft_commit(s, S, n));
+    HIP_TRY(c, record_tiles());
     HIP_TRY(c, phase_begin(c, s));
     HIP_TRY(c, launch_spread_tiles<T>(s, c->G, c->C_step, S, ff, n, nullptr, tile_cache()));
     HIP_TRY(c, phase_end(c, s, kSpread));
@@ -903,6 +917,8 @@ int prs_timing_read(prs_ctx *c, prs_timing *out, int reset) {
   out->n_substep = c->launches[kSubstep];
   out->ms_learned = c->ms[kLearned];
   out->n_learned = c->launches[kLearned];
+  out->ms_record = c->ms[kRecord];
+  out->n_record = c->launches[kRecord];
   if (reset) {
     for (int k = 0; k < kPhases; ++k) {
       c->ms[k] = 0.0;

@@ -1420,6 +1420,25 @@ template hipError_t launch_sphere_vmax<float>(hipStream_t, const Geom &, const S
 template hipError_t launch_sphere_vmax<double>(hipStream_t, const Geom &, const Scratch &, int,
                                                const double *);
 
+// The tiles' records alone (record-only form); the spreading passes that
+// follow replay them.
+template <typename T>
+hipError_t launch_tile_record(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
+                              int n) {
+  if (n == 0 || !S.tc_items) return hipSuccess;
+  const int ntiles = spread_tile_count<T>(G);
+  TileCache tc{1, S.tc_cap, S.tc_items, S.tc_count, S.tc_ncand};
+  hipLaunchKernelGGL((k_spread_tiles<T, 0, true>), dim3(xcd_grid(ntiles)), dim3(kRecordThreads),
+                     0, s, G, C, S.start, S.xs[0], n, S.templ,
+                     (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64),
+                     (const T *)S.dF, S.perm, S.vmax, nullptr, nullptr, nullptr, S.status, tc);
+  return hipGetLastError();
+}
+template hipError_t launch_tile_record<float>(hipStream_t, const Geom &, const Cells &,
+                                              const Scratch &, int);
+template hipError_t launch_tile_record<double>(hipStream_t, const Geom &, const Cells &,
+                                               const Scratch &, int);
+
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
                                T *f[3], int n, const T *src_caller, TileCache tc) {

@@ -188,6 +188,11 @@ size_t learned_lds_bytes(int nl, int nb, int esz);
 // Device buffers of a network (defined with the network).
 void mlp_buffers(const prs_mlp *mlp, LearnArgs *la);
 
+// Records of the spreading tiles (candidates and culled markers) for the
+// passes of a step that replay them.
+template <typename T>
+hipError_t launch_tile_record(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
+                              int n);
 template <typename T>
 hipError_t launch_spread_tiles(hipStream_t s, const Geom &G, const Cells &C, const Scratch &S,
                                T *f[3], int n, const T *src_caller, TileCache tc = TileCache{});
