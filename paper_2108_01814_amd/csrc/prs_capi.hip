@@ -500,6 +500,8 @@ int prs_create(const prs_params *p, prs_ctx **out) {
   rc |= alloc(c, &S.lane_order, (size_t)q.n_markers);
   rc |= alloc(c, &S.tm32, 8 * (size_t)q.n_markers);
   rc |= alloc(c, &S.tm64, 4 * (size_t)q.n_markers);
+  rc |= alloc(c, &S.tm32_lane, 8 * (size_t)q.n_markers);
+  rc |= alloc(c, &S.tm64_lane, 4 * (size_t)q.n_markers);
   if (rc != PRS_OK) {
     prs_destroy(c);
     return PRS_EHIP;
@@ -509,7 +511,8 @@ int prs_create(const prs_params *p, prs_ctx **out) {
     prs_destroy(c);
     return PRS_EHIP;
   }
-  if (launch_template(nullptr, S.templ, S.tm32, S.tm64, S.lane_order, q.n_markers,
+  if (launch_template(nullptr, S.templ, S.tm32, S.tm64, S.tm32_lane, S.tm64_lane, S.lane_order,
+                      q.n_markers,
                       q.radius / q.h) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     prs_destroy(c);

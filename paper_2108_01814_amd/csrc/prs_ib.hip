@@ -81,12 +81,24 @@ __global__ void k_marker_offsets(const double *t, int nl, double r_over_h, float
   tm64[4 * l + 3] = 0.0;
 }
 
-hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, int *lane_order,
-                           int nl, double r_over_h) {
+// The offsets in the interpolation's lane order.
+__global__ void k_lane_offsets(const int *order, const float *tm32, const double *tm64, int nl,
+                               float *tm32_lane, double *tm64_lane) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  const int l = order[i];
+  for (int k = 0; k < 8; ++k) tm32_lane[8 * i + k] = tm32[8 * l + k];
+  for (int k = 0; k < 4; ++k) tm64_lane[4 * i + k] = tm64[4 * l + k];
+}
+
+hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, float *tm32_lane,
+                           double *tm64_lane, int *lane_order, int nl, double r_over_h) {
   hipLaunchKernelGGL(k_template, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl);
   hipLaunchKernelGGL(k_lane_order, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl, lane_order);
   hipLaunchKernelGGL(k_marker_offsets, dim3((nl + 255) / 256), dim3(256), 0, s, t, nl, r_over_h,
                      tm32, tm64);
+  hipLaunchKernelGGL(k_lane_offsets, dim3((nl + 255) / 256), dim3(256), 0, s, lane_order, tm32,
+                     tm64, nl, tm32_lane, tm64_lane);
   return hipGetLastError();
 }
 
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(1024) void k_interp(
   // that interpolate u-hat record it in u0.
   const bool f_only = MODE == kInterpMDF && b0 != nullptr;
   T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
-  if (active) MarkerOffset<T>::load(tm, l, mhi, mlo);
+  if (active) MarkerOffset<T>::load(tm, threadIdx.x, mhi, mlo);   // tm in lane order
 
   constexpr int VEC = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
@@ -647,7 +659,8 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const Scratch &S, con
   const int nbuf = MODE == kInterpLearned ? 1 : interp_brick_buffers(nb, sizeof(T));
   size_t lds = brick_bytes(nb, sizeof(T)) * nbuf;
   if (MODE == kInterpLearned) lds = learned_lds_bytes(G.nl, nb, sizeof(T));
-  const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32 : (const void *)S.tm64);
+  // the marker offsets in lane order
+  const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32_lane : (const void *)S.tm64_lane);
 #define PRS_LAUNCH_INTERP(NBV)                                                                 \
   hipLaunchKernelGGL((k_interp<T, MODE, NBV>), grid, block, lds, s, G, S.templ, tm, a0, a1, a2, \
                      b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part,        \

@@ -104,6 +104,10 @@ struct Scratch {
   // xyz, pad, remainder xyz, pad) and [nl][4] doubles (xyz, pad)
   float *tm32;
   double *tm64;
+  // the same in the interpolation's lane order (entry i for marker
+  // lane_order[i]), so a lane's offsets load without the order lookup
+  float *tm32_lane;
+  double *tm64_lane;
   int *lane_order;                // [nl]: marker handled by interpolation lane i
 };
 
@@ -137,7 +141,8 @@ struct TileCache {
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, int *lane_order,
+hipError_t launch_template(hipStream_t s, double *t, float *tm32, double *tm64, float *tm32_lane,
+                           double *tm64_lane, int *lane_order,
                            int nl, double r_over_h);
 
 hipError_t launch_sort(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
