@@ -6,14 +6,19 @@ configurations.  It contains none of the method's arithmetic: no delta
 kernel, no forcing, no contact law, no integrator.  It is the one module that
 both the product tests and the oracle tests draw their inputs from.
 
-Bed recipe (the paper settles its beds with a sedimentation DEM, sec. 4.1,
-which is not reproduced here): spheres sit on a body-centred tetragonal
-lattice -- square layers of spacing a >= 1.02 D, alternate layers shifted by
-half a cell -- whose layer spacing is chosen so that each sphere overlaps its
-eight neighbours in the layers above and below by about 1e-4 D; the bottom
-layer overlaps the wall by 5e-5 D; a random subset of the sites is left empty
-so the bed volume fraction is about 0.58; every coordinate gets N(0, 1e-5 D)
-jitter.  Saltating spheres are placed above the bed by random sequential
+Bed recipe.  The paper settles its beds under gravity with its DEM
+(sec. 4.1).  The named workloads do the same: their beds are periodic copies
+of one patch (12 x 12 D for the million-sphere bed, 16 x 16 D and 8 x 8 D
+for the smaller ones) that the oracle's plain FP64 DEM let settle from a
+random column, stored as text under ``beds/`` by ``oracle/settle_beds.py``;
+a bed is the patch tiled over the box and shifted by a seeded periodic
+offset.  Reduced test workloads use a seeded lattice instead: spheres on a
+body-centred tetragonal lattice -- square layers of spacing a >= 1.02 D,
+alternate layers shifted by half a cell -- whose layer spacing is chosen so
+that each sphere overlaps its eight neighbours in the layers above and below
+by about 1e-4 D; the bottom layer overlaps the wall by 5e-5 D; a random
+subset of the sites is left empty so the bed volume fraction is about 0.58;
+every coordinate gets N(0, 1e-5 D) jitter.  Saltating spheres are placed above the bed by random sequential
 addition.  The fluid field is a log-law profile above the bed plus 32 seeded
 Fourier modes scaled to 10 % of the top velocity, convected with the mean
 velocity (frozen turbulence), so every step's field is regenerated from
@@ -23,6 +28,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -53,6 +59,7 @@ class Workload:
     upper_vy: tuple = (0.0, 0.1)   # (mean, std) of the saltating spheres' u_y
     bed_u_std: float = 0.01
     omega_std: float = 0.2
+    bed: str = ""                  # settled patch tiled into the bed ("" = lattice)
 
     @property
     def n(self) -> int:
@@ -74,12 +81,13 @@ class Workload:
 # C1: 512 spheres at D/h = 10 (the stated 8x4x8 D box cannot hold them; the
 # height is raised to 10 D).  C2: 22,000 spheres at D/h = 16.  C3: 1,048,576
 # spheres in the paper's own million-sphere domain, 384 x 20 x 192 D at
-# D/h = 10 (sec. 3.5).
+# D/h = 10 (sec. 3.5); its bed is 32 x 16 copies of a 1,946-sphere patch.
 C1 = Workload("c1-512", 384, 128, 10, 314, (8.0, 10.0, 8.0), seed=1, bed_u_std=0.1,
-              upper_vy=(0.0, 0.1))
-C2 = Workload("c2-22k", 20000, 2000, 16, 804, (64.0, 16.0, 32.0), seed=2, upper_vy=(1.0, 0.3))
-C3 = Workload("c3-1m", 996147, 52429, 10, 314, (384.0, 20.0, 192.0), seed=3, upper_band=10.0,
-              upper_vy=(1.0, 0.3))
+              upper_vy=(0.0, 0.1), bed="patch8-384")
+C2 = Workload("c2-22k", 20000, 2000, 16, 804, (64.0, 16.0, 32.0), seed=2, upper_vy=(1.0, 0.3),
+              bed_u_std=0.0, bed="patch16-2500")
+C3 = Workload("c3-1m", 996352, 52224, 10, 314, (384.0, 20.0, 192.0), seed=3, upper_band=10.0,
+              upper_vy=(1.0, 0.3), bed_u_std=0.0, bed="patch12-1946")
 WORKLOADS = {w.name: w for w in (C1, C2, C3)}
 
 
@@ -120,6 +128,37 @@ def _lattice_bed(rng, n_bed, Lx, Lz, D, overlap=1e-4, wall_overlap=5e-5, phi=0.5
     x[:, 1] = np.maximum(x[:, 1], 0.5 * D - 2 * wall_overlap)
     x[:, 0] = np.mod(x[:, 0], Lx)
     x[:, 2] = np.mod(x[:, 2], Lz)
+    return x
+
+
+BED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "beds")
+
+
+def load_patch(name: str):
+    """A settled bed patch: (positions [m, 3], edge in x and z)."""
+    path = os.path.join(BED_DIR, name + ".txt")
+    with open(path) as fh:
+        head = fh.readline()
+    edge = float(head.split("periodic ")[1].split(" x ")[0])
+    return np.loadtxt(path, dtype=np.float64, ndmin=2), edge
+
+
+def _patch_bed(rng, name, n_bed, Lx, Lz):
+    """Copies of a settled periodic patch over the box, shifted by a seeded
+    offset in x and z (a translation of a periodic bed is a settled bed)."""
+    xp, edge = load_patch(name)
+    cx, cz = Lx / edge, Lz / edge
+    if abs(cx - round(cx)) > 1e-12 or abs(cz - round(cz)) > 1e-12:
+        raise ValueError(f"patch {name} does not tile a {Lx} x {Lz} box")
+    cx, cz = int(round(cx)), int(round(cz))
+    if n_bed != cx * cz * len(xp):
+        raise ValueError(f"patch {name} gives {cx * cz * len(xp)} bed spheres, not {n_bed}")
+    ix, iz = np.meshgrid(np.arange(cx), np.arange(cz), indexing="ij")
+    off = np.stack([ix.ravel() * edge, np.zeros(cx * cz), iz.ravel() * edge], axis=1)
+    x = (off[:, None, :] + xp[None, :, :]).reshape(-1, 3)
+    shift = rng.uniform(0.0, 1.0, size=2) * np.array([Lx, Lz])
+    x[:, 0] = np.mod(x[:, 0] + shift[0], Lx)
+    x[:, 2] = np.mod(x[:, 2] + shift[1], Lz)
     return x
 
 
@@ -180,7 +219,10 @@ def make_bed(w: Workload, seed: Optional[int] = None) -> Bed:
     rng = np.random.default_rng(w.seed if seed is None else seed)
     D = PHYS["D"]
     Lx, Ly, Lz = w.domain
-    xb = _lattice_bed(rng, w.n_bed, Lx, Lz, D)
+    if w.bed:
+        xb = _patch_bed(rng, w.bed, w.n_bed, Lx, Lz)
+    else:
+        xb = _lattice_bed(rng, w.n_bed, Lx, Lz, D)
     top = float(xb[:, 1].max() + 0.5 * D) if w.n_bed else 0.0
     y_lo = top + 0.5 * D
     y_hi = min(top + w.upper_band, Ly - 0.5 * D - 1e-3)
@@ -190,7 +232,9 @@ def make_bed(w: Workload, seed: Optional[int] = None) -> Bed:
                         np.stack([rng.normal(0.0, 0.1, w.n_upper),
                                   rng.normal(w.upper_vy[0], w.upper_vy[1], w.n_upper),
                                   rng.normal(0.0, 0.1, w.n_upper)], axis=1)], axis=0)
-    om = rng.normal(0.0, w.omega_std if w.bed_u_std >= 0.1 else 0.02, size=(w.n, 3))
+    # a settled bed at rest (bed_u_std 0) starts without spin as well
+    om_bed = w.omega_std if w.bed_u_std >= 0.1 else (0.02 if w.bed_u_std > 0 else 0.0)
+    om = rng.normal(0.0, om_bed, size=(w.n, 3))
     om[w.n_bed:] = rng.normal(0.0, w.omega_std, size=(w.n_upper, 3))
     perm = rng.permutation(w.n)   # callers see particles in no spatial order
     return Bed(np.ascontiguousarray(x[perm]), np.ascontiguousarray(u[perm]),

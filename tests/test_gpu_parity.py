@@ -133,7 +133,8 @@ def test_contacts_bit_exact_c1(P, orc):
     with P.Context(prs_params(P, w, P.F64)) as ctx:
         pairs = ctx.contacts(dev(bed.x)).cpu().numpy()
     rc, ref, n = orc.contacts(oracle_params(orc, w, use_cells=0), bed.x)
-    assert rc == 0 and n == len(pairs) > 1000
+    # the settled C1 bed lists about 1.7 contacts per sphere (each pair once)
+    assert rc == 0 and n == len(pairs) > 800
     assert np.array_equal(pairs, ref)
 
 
