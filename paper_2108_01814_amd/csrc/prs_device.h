@@ -44,6 +44,8 @@ enum : int {
   kDppMirror = 0x140,       // lane i <- 15 - i within each row
   kDppBcast15 = 0x142,      // lane 15 of each row -> the next row
   kDppBcast31 = 0x143,      // lane 31 -> rows 2 and 3
+  kDppRor4 = 0x124,         // lane i <- (i + 4) mod 16 within each row
+  kDppRor8 = 0x128,         // lane i <- (i + 8) mod 16 within each row
 };
 
 // One 32-bit word: with every row written (ROW_MASK 0xF) the plain move,
@@ -86,14 +88,19 @@ __device__ inline T wave_sum_last(T v) {
   return v;
 }
 
-// nan_max over the wave of non-negative values (or NaN), valid in lane 63.
-__device__ inline float wave_nanmax_last(float v) {
-  v = nan_max(v, dpp_move<kDppXor1, 0xF>(v));
-  v = nan_max(v, dpp_move<kDppXor2, 0xF>(v));
-  v = nan_max(v, dpp_move<kDppHalfMirror, 0xF>(v));
-  v = nan_max(v, dpp_move<kDppMirror, 0xF>(v));
-  v = nan_max(v, dpp_move<kDppBcast15, 0xA>(v));
-  v = nan_max(v, dpp_move<kDppBcast31, 0xC>(v));
+// |v| as its bit pattern: for values with the sign bit clear the unsigned
+// order of the patterns is the numeric order, and every NaN sorts above
+// +inf, so the largest pattern is the largest |v| or a NaN.
+__device__ inline unsigned abs_bits(float v) { return __float_as_uint(fabsf(v)); }
+
+// Largest pattern over the wave, valid in lane 63.
+__device__ inline unsigned wave_max_last(unsigned v) {
+  v = max(v, (unsigned)dpp_move<kDppXor1, 0xF>((int)v));
+  v = max(v, (unsigned)dpp_move<kDppXor2, 0xF>((int)v));
+  v = max(v, (unsigned)dpp_move<kDppHalfMirror, 0xF>((int)v));
+  v = max(v, (unsigned)dpp_move<kDppMirror, 0xF>((int)v));
+  v = max(v, (unsigned)dpp_move<kDppBcast15, 0xA>((int)v));
+  v = max(v, (unsigned)dpp_move<kDppBcast31, 0xC>((int)v));
   return v;
 }
 

@@ -205,9 +205,9 @@ template <typename T, int MODE, int NB>
 __global__ __launch_bounds__(1024) void k_interp(
     Geom G, const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, const T *__restrict__ b0,
-    const T *__restrict__ b1, const T *__restrict__ b2, double adt, const double *__restrict__ xs,
-    const double *__restrict__ us, const double *__restrict__ ws, int n, int nb,
-    T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
+    const T *__restrict__ b1, const T *__restrict__ b2, double adt, double inv_adt,
+    const double *__restrict__ xs, const double *__restrict__ us, const double *__restrict__ ws,
+    int n, int nb, T *__restrict__ out, T *__restrict__ out2, double *__restrict__ slip_part,
     double *__restrict__ ft_part, const int *__restrict__ order, LearnArgs la,
     float *__restrict__ vmax_out, T *__restrict__ u0, int nbuf) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_interp(
   // otherwise reloaded from the dispatch packet, and that load's wait would
   // also wait for the brick loads in flight)
   const int bdim = (int)blockDim.x;
-  const int wave_base = (int)(threadIdx.x & ~63u);
+  const int wave_base = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;   // scalar
   const int p = xcd_item(blockIdx.x, n);
   if (p < 0) return;
   const bool active = (int)threadIdx.x < G.nl;
@@ -242,7 +242,9 @@ __global__ __launch_bounds__(1024) void k_interp(
     }
   }
   const T tadt = (T)adt;
-  const T inv_tadt = (T)(1.0 / adt);   // the correction r / (alpha dt) by multiplication
+  // the correction r / (alpha dt) by multiplication (1 / (alpha dt) from the
+  // host: a division here would be a per-lane FP64 sequence)
+  const T inv_tadt = (T)inv_adt;
   // An MDF pass over a nonzero f interpolates f alone and adds the step's
   // recorded I[u-hat] (the interpolation is linear: I[u-hat + adt f] =
   // I[u-hat] + adt I[f]), so it loads one field instead of two; the passes
@@ -274,11 +276,13 @@ __global__ __launch_bounds__(1024) void k_interp(
   // bricks share the origin), two registers each: the node plane k (wrapped)
   // with flags in the top bits (bit 28: row inside the fluid for u and w,
   // bit 29: for v, bit 30: the chunk crosses the periodic x seam, bit 31:
-  // slot in use), and the offset j nx + x0 of the chunk within the plane
+  // slot in use), and the chunk's element offset (k ny + j) nx + x0 in the
+  // u and w arrays; in the v array (ny + 1 rows a plane) it is k nx more.
+  // Element offsets fit 32 bits (a component holds fewer than 2^32 nodes).
   constexpr int kSlots = BrickSlots<T>::value;
   constexpr unsigned kFuw = 1u << 28, kFv = 1u << 29, kFseam = 1u << 30, kFuse = 1u << 31;
   unsigned sK[kSlots];
-  int sJX[kSlots];
+  unsigned sOff[kSlots];
 #pragma unroll
   for (int u = 0; u < kSlots; ++u) {
     const int it = threadIdx.x + u * bdim;
@@ -289,23 +293,30 @@ __global__ __launch_bounds__(1024) void k_interp(
     sK[u] = (unsigned)wrap_once(lo[2] + bz, G.nz) | (j >= 0 && j <= G.ny - 1 ? kFuw : 0u) |
             (j >= 1 && j <= G.ny - 1 ? kFv : 0u) |
             (x0 < 0 || x0 + VEC > G.nx ? kFseam : 0u) | (it < per_comp ? kFuse : 0u);
-    sJX[u] = j * G.nx + x0;
+    sOff[u] = (unsigned)wrap_once(lo[2] + bz, G.nz) * (unsigned)(G.ny * G.nx) +
+              (unsigned)(j * G.nx + x0);
   }
   // rows per node plane of component c (v has ny + 1 rows)
   auto nyc = [&](int c) { return c == 1 ? G.ny + 1 : G.ny; };
+  // element offset of slot u's chunk in component c's array (the plane
+  // index is below 2^24, so k nx takes one 24-bit multiply)
+  auto chunk_offset = [&](int c, int u) -> unsigned {
+    return c == 1 ? sOff[u] + __umul24(sK[u] & (kFuw - 1u), (unsigned)G.nx)
+                  : sOff[u];
+  };
   auto load_slot = [&](int c, int u) {
     vec_t v = (vec_t)(T)0;
     const unsigned fl = sK[u];
     if ((fl & kFuse) && (fl & (c == 1 ? kFv : kFuw))) {
       const T *Sp = f_only ? (c == 0 ? b0 : (c == 1 ? b1 : b2)) : (c == 0 ? a0 : (c == 1 ? a1 : a2));
-      const size_t plane = (size_t)(fl & (kFuw - 1u)) * (size_t)nyc(c) * (size_t)G.nx;
       if (!(fl & kFseam)) {
-        __builtin_memcpy(&v, Sp + plane + (size_t)(long)sJX[u], sizeof(vec_t));
+        __builtin_memcpy(&v, Sp + chunk_offset(c, u), sizeof(vec_t));
       } else {
         // the chunk crosses the seam: elements wrapped one by one
         const int it = threadIdx.x + u * bdim;
         const int row = it / CPR, ch = it - row * CPR;
         const int by = row - (row / nb) * nb;
+        const size_t plane = (size_t)(fl & (kFuw - 1u)) * (size_t)nyc(c) * (size_t)G.nx;
         const T *rowp = Sp + plane + (size_t)(long)((lo[1] + by) * G.nx);
         const int x0 = lo[0] + ch * VEC;
 #pragma unroll
@@ -362,8 +373,7 @@ __global__ __launch_bounds__(1024) void k_interp(
     for (int u = 0; u < kSlots; ++u) {
       const unsigned fl = sK[u];
       if ((fl & kFuse) && (fl & in_flag) && !(fl & kFseam)) {
-        const size_t plane = (size_t)(fl & (kFuw - 1u)) * (size_t)nyc(c) * (size_t)G.nx;
-        lds_load16(Sp + plane + (size_t)(long)sJX[u], buf + (u * bdim + wave_base) * VEC);
+        lds_load16(Sp + chunk_offset(c, u), buf + (u * bdim + wave_base) * VEC);
       }
     }
   };
@@ -534,7 +544,7 @@ __global__ __launch_bounds__(1024) void k_interp(
   }
   Red red;
   red_zero(red);
-  float vm = 0.f;   // largest |value| this lane writes to out (MDF, learned)
+  unsigned vm = 0u;   // largest |value| this lane writes to out (MDF, learned), abs_bits
   // features of the learned warm start: slip, normal, u_p, R omega_p
   double featd[kMlpFeat];
   if (MODE == kInterpFeat || MODE == kInterpLearned) {
@@ -587,14 +597,13 @@ __global__ __launch_bounds__(1024) void k_interp(
     if (active) {
       // de-standardise in FP64: F0 = (y std + mean) / (alpha dt)
       const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
-      const double inv_adt = 1.0 / adt;
       double d[3];
       for (int c = 0; c < 3; ++c) {
         const double y = (double)yl[threadIdx.x * kMlpUsed + c];
         const T f0 = (T)((y * (double)la.norm[2 * kMlpIn + kMlpUsed + c] +
                           (double)la.norm[2 * kMlpIn + c]) * inv_adt);
         out[c * M + m] = f0;
-        vm = nan_max(vm, fabsf((float)f0));
+        vm = max(vm, abs_bits((float)f0));
         d[c] = (double)f0;
       }
       red_set_ft(red, rl, d);
@@ -608,7 +617,7 @@ __global__ __launch_bounds__(1024) void k_interp(
         const T res = (T)Ud[c] - U[c];
         const T corr = res * inv_tadt;
         out[c * M + m] = corr;
-        vm = nan_max(vm, fabsf((float)corr));
+        vm = max(vm, abs_bits((float)corr));
         d[c] = (double)corr;
         red.v[kColSlip] += (double)res * (double)res;
       }
@@ -623,8 +632,8 @@ __global__ __launch_bounds__(1024) void k_interp(
   __shared__ float s_vmax[16];
   constexpr bool kForce = MODE == kInterpMDF || MODE == kInterpLearned;
   if (kForce) {
-    vm = wave_nanmax_last(vm);
-    if ((threadIdx.x & 63) == 63) s_vmax[threadIdx.x >> 6] = vm;
+    vm = wave_max_last(vm);
+    if ((threadIdx.x & 63) == 63) s_vmax[threadIdx.x >> 6] = __uint_as_float(vm);
   }
   constexpr unsigned kMask = (kForce ? 0x3Fu : 0u) |
                              (MODE == kInterpMDF ? 1u << kColSlip : 1u << kColSlip0);
@@ -661,10 +670,11 @@ hipError_t launch_interp_any(hipStream_t s, const Geom &G, const Scratch &S, con
   if (MODE == kInterpLearned) lds = learned_lds_bytes(G.nl, nb, sizeof(T));
   // the marker offsets in lane order
   const T *tm = (const T *)(sizeof(T) == 4 ? (const void *)S.tm32_lane : (const void *)S.tm64_lane);
+  const double inv_adt = adt != 0.0 ? 1.0 / adt : 0.0;
 #define PRS_LAUNCH_INTERP(NBV)                                                                 \
   hipLaunchKernelGGL((k_interp<T, MODE, NBV>), grid, block, lds, s, G, S.templ, tm, a0, a1, a2, \
-                     b0, b1, b2, adt, xs, us, ws, n, nb, out, out2, slip_part, ft_part,        \
-                     S.lane_order, la, vmax_out, u0, nbuf)
+                     b0, b1, b2, adt, inv_adt, xs, us, ws, n, nb, out, out2, slip_part,        \
+                     ft_part, S.lane_order, la, vmax_out, u0, nbuf)
   if (nb == 14)
     PRS_LAUNCH_INTERP(14);
   else if (nb == 20)
@@ -819,10 +829,19 @@ struct TileAcc<float> {
 // without tests (the band's sums are discarded).  Only the tile's own rows
 // take LDS, which keeps three tiles resident per compute unit.
 constexpr int kGuard = 2;
+// Padding of the accumulator's rows and planes in entries (knobs of the LDS
+// bank mapping).
+#ifndef PRS_ACC_ROW_PAD
+#define PRS_ACC_ROW_PAD 0
+#endif
+#ifndef PRS_ACC_PLANE_PAD
+#define PRS_ACC_PLANE_PAD 0
+#endif
 template <int TX, int TY, int TZ>
 struct AccLayout {
-  static constexpr int PX = TX + 2 * kGuard;
-  static constexpr int NODES = PX * TY * TZ;   // per component
+  static constexpr int PX = TX + 2 * kGuard + PRS_ACC_ROW_PAD;   // row stride
+  static constexpr int PZ = PX * TY + PRS_ACC_PLANE_PAD;         // plane stride
+  static constexpr int NODES = PZ * TZ;   // per component
 };
 
 constexpr int kTileCand = 256;     // spheres gathered by one tile
@@ -912,7 +931,8 @@ __device__ inline void spread_visit_v(const Geom &G, const int d[3], const T fo[
                                       const T *__restrict__ tm, const T v[3], int l, T scale,
                                       typename TileAcc<T>::type *acc) {
   using A_t = typename TileAcc<T>::type;
-  constexpr int PX = AccLayout<TX, TY, TZ>::PX, NODES = AccLayout<TX, TY, TZ>::NODES;
+  constexpr int PX = AccLayout<TX, TY, TZ>::PX, PZ = AccLayout<TX, TY, TZ>::PZ,
+                NODES = AccLayout<TX, TY, TZ>::NODES;
   T mhi[3], mlo[3];
   MarkerOffset<T>::load(tm, l, mhi, mlo);
   int b[3][2];
@@ -942,7 +962,7 @@ __device__ inline void spread_visit_v(const Geom &G, const int d[3], const T fo[
       for (int jj = 0; jj < 3; ++jj) {
         if ((unsigned)(y0 + jj) >= (unsigned)TY) continue;
         const W_t vzy = vz * (W_t)wy[jj];
-        A_t *row = Ac + ((z0 + kk) * TY + (y0 + jj)) * PX;
+        A_t *row = Ac + (z0 + kk) * PZ + (y0 + jj) * PX;
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
           if constexpr (std::is_integral<A_t>::value)
@@ -1010,7 +1030,8 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
                                   double unit, bool poison, bool overwrite, T *f0, T *f1, T *f2,
                                   uint32_t *status) {
   constexpr bool kFixed = std::is_integral<A_t>::value;
-  constexpr int PX = AccLayout<TX, TY, TZ>::PX, NODES = AccLayout<TX, TY, TZ>::NODES;
+  constexpr int PX = AccLayout<TX, TY, TZ>::PX, PZ = AccLayout<TX, TY, TZ>::PZ,
+                NODES = AccLayout<TX, TY, TZ>::NODES;
   static_assert((TX & (TX - 1)) == 0 && kTileThreads % TX == 0, "x-rows of the tile");
   constexpr int kRows = 3 * TZ * TY, kStep = kTileThreads / TX;
   constexpr int kPer = (kRows + kStep - 1) / kStep;   // rows per lane
@@ -1038,7 +1059,7 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
     const int lz = lz0 + dz;
     if (!lane_ok || j >= nyc || k0 + lz >= G.nz) return false;
     wall = c == 1 && (j == 0 || j == G.ny);
-    a = (acc && !wall) ? acc[c * NODES + (lz * TY + ly) * PX + lx + kGuard] : (A_t)0;
+    a = (acc && !wall) ? acc[c * NODES + lz * PZ + ly * PX + lx + kGuard] : (A_t)0;
     if (wall ? !overwrite : (a == (A_t)0 && !poison && !overwrite)) return false;
     g = (c == 1 ? base_v : base_uw) + (size_t)dz * ((size_t)nyc * (size_t)G.nx);
     Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
@@ -1406,18 +1427,18 @@ __global__ __launch_bounds__(1024) void k_sphere_vmax(Geom G, const T *__restric
   __shared__ float wm[16];
   const int p = xcd_item(blockIdx.x, n);
   if (p < 0) return;
-  float m = 0.f;
+  unsigned m = 0u;
   if ((int)threadIdx.x < G.nl) {
     const size_t q = ((size_t)perm[p] * G.nl + threadIdx.x) * 3;
-    for (int c = 0; c < 3; ++c) m = nan_max(m, fabsf((float)F[q + c]));
+    for (int c = 0; c < 3; ++c) m = max(m, abs_bits((float)F[q + c]));
   }
-  m = wave_nanmax_last(m);
-  if ((threadIdx.x & 63) == 63) wm[threadIdx.x >> 6] = m;
+  m = wave_max_last(m);
+  if ((threadIdx.x & 63) == 63) wm[threadIdx.x >> 6] = __uint_as_float(m);
   __syncthreads();
   if (threadIdx.x == 0) {
-    m = wm[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = nan_max(m, wm[w]);
-    vmax[p] = m;
+    float mf = wm[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mf = nan_max(mf, wm[w]);
+    vmax[p] = mf;
   }
 }
 

@@ -114,6 +114,42 @@ __device__ inline void red_set_ft(Red &r, const double rl[3], const double d[3])
   r.v[5] = rl[0] * d[1] - rl[1] * d[0];
 }
 
+// Wave sums of eight columns at once, each step halving the columns a lane
+// carries: a lane keeps one half and adds its partner's copy of that half
+// (partners differ in lane bit 0, then bit 1), so the last four steps move
+// two values instead of eight.  The steps over lane bits 2 and 3 rotate
+// within a row, those over bits 4 and 5 cross rows through the LDS
+// crossbar.  On return every lane holds the wave sums of columns
+// 4 b0 + 2 b1 and 4 b0 + 2 b1 + 1 (b0, b1: bits 0 and 1 of its lane), in
+// w0 and w1.  Every lane of the wave must be active.
+__device__ inline void wave_sum8(const double v[8], double &w0, double &w1) {
+  const int lane = threadIdx.x & 63;
+  const bool b0 = lane & 1, b1 = (lane >> 1) & 1;
+  double a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = b0 ? v[i + 4] : v[i];
+    const double send = b0 ? v[i] : v[i + 4];
+    a[i] = keep + dpp_move<kDppXor1, 0xF>(send);
+  }
+  double b[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = b1 ? a[i + 2] : a[i];
+    const double send = b1 ? a[i] : a[i + 2];
+    b[i] = keep + dpp_move<kDppXor2, 0xF>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    b[i] += dpp_move<kDppRor4, 0xF>(b[i]);
+    b[i] += dpp_move<kDppRor8, 0xF>(b[i]);
+    b[i] += __shfl_xor(b[i], 16);
+    b[i] += __shfl_xor(b[i], 32);
+  }
+  w0 = b[0];
+  w1 = b[1];
+}
+
 // Block sums of the columns in MASK: a plain FP64 sum inside each wave (at
 // most 6 roundings per term, far below the single-precision inputs' own
 // error), compensated across waves.  On return thread t < 8 holds column t's
@@ -124,13 +160,23 @@ __device__ inline void block_reduce(Red &r, double &s, double &c) {
   __shared__ double lds[16][8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if ((MASK >> k) & 1u) r.v[k] = wave_sum_last(r.v[k]);
-  if (lane == 63) {
+  if constexpr (__builtin_popcount(MASK) >= 4) {
+    double w0, w1;
+    wave_sum8(r.v, w0, w1);
+    if (lane < 4) {
+      const int c0 = 4 * (lane & 1) + 2 * (lane >> 1);
+      if ((MASK >> c0) & 1u) lds[wave][c0] = w0;
+      if ((MASK >> (c0 + 1)) & 1u) lds[wave][c0 + 1] = w1;
+    }
+  } else {
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if ((MASK >> k) & 1u) lds[wave][k] = r.v[k];
+      if ((MASK >> k) & 1u) r.v[k] = wave_sum_last(r.v[k]);
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if ((MASK >> k) & 1u) lds[wave][k] = r.v[k];
+    }
   }
   __syncthreads();
   s = c = 0.0;
