@@ -110,7 +110,8 @@ def run_form(P, W, w, bed, precision, steps, warmup, torch, measure_touched=Fals
             res["touched"] = touched_nodes(ctx, x0, torch)
             log(f"touched nodes per component: {res['touched']}")
         x, u, om = x0.clone(), u0.clone(), om0.clone()
-        H = P.History.zeros(w.n)
+        # a settled bed starts from its contact history at rest
+        H = P.History.from_host(bed.hist) if bed.hist is not None else P.History.zeros(w.n)
         Fh = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
         Th = torch.empty_like(Fh)
         for k in range(warmup):
@@ -146,12 +147,13 @@ def time_single_steps(P, ctx, uhat, bed, K, torch):
     f = [torch.empty_like(a) for a in uhat]
     Fh = torch.empty((n, 3), dtype=torch.float64, device="cuda")
     Th = torch.empty_like(Fh)
+    H0 = P.History.from_host(bed.hist) if bed.hist is not None else P.History.zeros(n)
     total = 0.0
     ctx.timing(True)
     ctx.read_timing(reset=True)
     for _ in range(K):
         x, u, om = x0.clone(), u0.clone(), om0.clone()
-        H = P.History.zeros(n)
+        H = H0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, st = ctx.step(uhat, f, x, u, om, H, Fh, Th, zero_f=True)

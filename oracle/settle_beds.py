@@ -17,7 +17,10 @@ App. A), in a box that is periodic in x and z with a wall at y = 0:
 
 The stiffness, gravity, densities and friction are those of the workloads,
 so a settled patch is at rest under the coupled runs' contact law too (its
-overlaps balance the same weights).  Usage:
+overlaps and tangential springs balance the same weights).  The contact
+history at rest (partners, tangential displacements, impact velocities) is
+stored with the positions, so a run can start from the settled state
+itself rather than from unloaded tangential springs.  Usage:
 
     python -m oracle.settle_beds [name ...]
 """
@@ -88,21 +91,36 @@ def settle(edge: float, n: int, seed: int, log=print):
     contacts = int(hist.cnt.sum())
     log(f"  at rest after {calls * n_sub} substeps: coordination {contacts / n:.2f}, "
         f"top {x[:, 1].max() + 0.5 * D:.2f} D")
-    return x
+    return x, hist
 
 
 def write_patch(name: str):
     edge, n, seed = PATCHES[name]
     print(f"{name}: {n} spheres, {edge} x {edge} D, seed {seed}")
-    x = settle(edge, n, seed)
+    x, hist = settle(edge, n, seed)
     order = np.lexsort((x[:, 2], x[:, 0], x[:, 1]))
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
     os.makedirs(OUT_DIR, exist_ok=True)
     path = os.path.join(OUT_DIR, name + ".txt")
     header = (f"bed patch {name}: {n} spheres of diameter 1, periodic {edge} x {edge} in x and z, "
               f"wall at y = 0; settled under buoyant gravity by the oracle's DEM "
               f"(python -m oracle.settle_beds {name}, seed {seed}); columns x y z")
     np.savetxt(path, x[order], fmt="%.17g", header=header)
-    print(f"  wrote {path}")
+    # the contact history at rest, one row per contact slot, sphere indices
+    # in the order of the positions file; partner -1: the bottom wall
+    rows = []
+    for i in range(n):
+        p = order[i]
+        for k in range(hist.cnt[p]):
+            q = int(hist.partner[p, k])
+            rows.append([i, rank[q] if q >= 0 else q, *hist.dt[p, k], hist.uin[p, k]])
+    hpath = os.path.join(OUT_DIR, name + ".hist.txt")
+    hheader = (f"contact history of bed patch {name} at rest (python -m oracle.settle_beds "
+               f"{name}); columns: sphere, partner (-1 bottom wall), delta_t x y z, u_in")
+    np.savetxt(hpath, np.array(rows), fmt=["%d", "%d", "%.12g", "%.12g", "%.12g", "%.12g"],
+               header=hheader)
+    print(f"  wrote {path} and {hpath}")
 
 
 if __name__ == "__main__":

@@ -197,6 +197,17 @@ class History:
                    torch.zeros((n, SLOTS), dtype=torch.float64, device=device),
                    torch.zeros((n,), dtype=torch.int8, device=device))
 
+    @classmethod
+    def from_host(cls, h: dict, device="cuda"):
+        """Device copy of a history given as host arrays (partner, delta_t,
+        u_in, count in the layout of prs_history)."""
+        import torch
+
+        return cls(torch.as_tensor(h["partner"], dtype=torch.int32).to(device),
+                   torch.as_tensor(h["delta_t"], dtype=torch.float64).to(device),
+                   torch.as_tensor(h["u_in"], dtype=torch.float64).to(device),
+                   torch.as_tensor(h["count"], dtype=torch.int8).to(device))
+
     def clone(self):
         return History(self.partner.clone(), self.delta_t.clone(), self.u_in.clone(),
                        self.count.clone())

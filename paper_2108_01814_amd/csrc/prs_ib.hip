@@ -115,6 +115,11 @@ size_t brick_bytes(int nb, int esz) {
 #define PRS_INTERP_DMA 1
 #endif
 
+// Brick chunks that no stencil of the sphere reads skipped (1) or loaded (0).
+#ifndef PRS_INTERP_CULL
+#define PRS_INTERP_CULL 1
+#endif
+
 static inline int block_for(int nl) { return ((nl + 63) / 64) * 64; }
 
 // Brick buffers of the interpolation: two (the next component's brick loads
@@ -283,6 +288,30 @@ __global__ __launch_bounds__(1024) void k_interp(
   constexpr unsigned kFuw = 1u << 28, kFv = 1u << 29, kFseam = 1u << 30, kFuse = 1u << 31;
   unsigned sK[kSlots];
   unsigned sOff[kSlots];
+  // Chunks that no stencil of this sphere reads are not loaded (slot marked
+  // unused): a stencil reads the nodes within 1.5 node of its marker along
+  // each axis, and the markers lie on the sphere of radius R / h about the
+  // centre, so a chunk is read only if the box of its nodes -- over the
+  // three components' staggerings, widened by 1.5 -- meets that sphere:
+  // nearest corner within and farthest corner beyond R / h (with a margin
+  // for the rounding of the marker offsets).
+  const float c_x = (float)E + (float)fo[0][0], c_y = (float)E + (float)fo[1][0],
+              c_z = (float)E + (float)fo[2][0];
+  const float rh = (float)(G.R * G.inv_h);
+  const float r_in = (rh - 0.01f) * (rh - 0.01f), r_out = (rh + 0.01f) * (rh + 0.01f);
+  auto chunk_read = [&](int bx0, int by, int bz) {
+    auto axis = [](float c, float lo, float hi, float &near2, float &far2) {
+      const float a = lo - c, b = c - hi;
+      const float e = fmaxf(fmaxf(a, b), 0.0f), g = fmaxf(fabsf(a), fabsf(b));
+      near2 = fmaf(e, e, near2);
+      far2 = fmaf(g, g, far2);
+    };
+    float near2 = 0.0f, far2 = 0.0f;
+    axis(c_x, (float)bx0 - 1.5f, (float)(bx0 + VEC - 1) + 2.0f, near2, far2);
+    axis(c_y, (float)by - 1.5f, (float)by + 2.0f, near2, far2);
+    axis(c_z, (float)bz - 1.5f, (float)bz + 2.0f, near2, far2);
+    return near2 <= r_out && far2 >= r_in;
+  };
 #pragma unroll
   for (int u = 0; u < kSlots; ++u) {
     const int it = threadIdx.x + u * bdim;
@@ -290,9 +319,10 @@ __global__ __launch_bounds__(1024) void k_interp(
     const int bz = row / nb, by = row - bz * nb;
     const int j = lo[1] + by;
     const int x0 = lo[0] + ch * VEC;
+    const bool read = !PRS_INTERP_CULL || chunk_read(ch * VEC, by, bz);
     sK[u] = (unsigned)wrap_once(lo[2] + bz, G.nz) | (j >= 0 && j <= G.ny - 1 ? kFuw : 0u) |
             (j >= 1 && j <= G.ny - 1 ? kFv : 0u) |
-            (x0 < 0 || x0 + VEC > G.nx ? kFseam : 0u) | (it < per_comp ? kFuse : 0u);
+            (x0 < 0 || x0 + VEC > G.nx ? kFseam : 0u) | (it < per_comp && read ? kFuse : 0u);
     sOff[u] = (unsigned)wrap_once(lo[2] + bz, G.nz) * (unsigned)(G.ny * G.nx) +
               (unsigned)(j * G.nx + x0);
   }
@@ -829,13 +859,18 @@ struct TileAcc<float> {
 // without tests (the band's sums are discarded).  Only the tile's own rows
 // take LDS, which keeps three tiles resident per compute unit.
 constexpr int kGuard = 2;
-// Padding of the accumulator's rows and planes in entries (knobs of the LDS
-// bank mapping).
+// Padding of the accumulator's rows and planes in entries: the LDS bank of
+// an entry follows its offset, and unpadded planes (160 entries in FP32)
+// put the same node of different planes in one bank, so lanes adding at
+// the same (x, y) of different planes conflict.  Eight entries a plane took
+// the single-precision spreading pass from 15.8 to 14.5 ms at C3 (padding
+// the rows instead, or the planes by 2 to 16 entries, gave 14.5 to 14.9 ms;
+// 36 entries left two tiles per compute unit).
 #ifndef PRS_ACC_ROW_PAD
 #define PRS_ACC_ROW_PAD 0
 #endif
 #ifndef PRS_ACC_PLANE_PAD
-#define PRS_ACC_PLANE_PAD 0
+#define PRS_ACC_PLANE_PAD 8
 #endif
 template <int TX, int TY, int TZ>
 struct AccLayout {

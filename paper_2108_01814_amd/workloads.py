@@ -18,11 +18,12 @@ alternate layers shifted by half a cell -- whose layer spacing is chosen so
 that each sphere overlaps its eight neighbours in the layers above and below
 by about 1e-4 D; the bottom layer overlaps the wall by 5e-5 D; a random
 subset of the sites is left empty so the bed volume fraction is about 0.58;
-every coordinate gets N(0, 1e-5 D) jitter.  Saltating spheres are placed above the bed by random sequential
-addition.  The fluid field is a log-law profile above the bed plus 32 seeded
-Fourier modes scaled to 10 % of the top velocity, convected with the mean
-velocity (frozen turbulence), so every step's field is regenerated from
-(seed, step).
+every coordinate gets N(0, 1e-5 D) jitter.  Saltating spheres are placed
+above the bed by random sequential addition.  The fluid field is a log-law
+profile above the bed plus 32 seeded Fourier modes scaled to 10 % of the top
+velocity, faded out over the diameter below the bed top (the fluid inside a
+settled bed is at rest with it), convected with the mean velocity (frozen
+turbulence), so every step's field is regenerated from (seed, step).
 """
 from __future__ import annotations
 
@@ -132,6 +133,10 @@ def _lattice_bed(rng, n_bed, Lx, Lz, D, overlap=1e-4, wall_overlap=5e-5, phi=0.5
 
 
 BED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "beds")
+# Layout of the step's contact history (prs_history): slots per sphere and
+# the partner code of the bottom wall.
+SLOTS = 14
+WALL_BOTTOM = -1
 
 
 def load_patch(name: str):
@@ -143,9 +148,41 @@ def load_patch(name: str):
     return np.loadtxt(path, dtype=np.float64, ndmin=2), edge
 
 
+def load_patch_history(name: str):
+    """The contact history of a settled patch at rest: rows (sphere, partner
+    or -1 for the bottom wall, delta_t x y z, u_in), or None if not stored."""
+    path = os.path.join(BED_DIR, name + ".hist.txt")
+    if not os.path.exists(path):
+        return None
+    return np.loadtxt(path, dtype=np.float64, ndmin=2)
+
+
+def _tile_history(xp, edge, rows, cx, cz):
+    """The patch history on every copy: (owner, partner, delta_t [3], u_in)
+    with bed indices copy * m + i; a partner across the patch's periodic seam
+    is the neighbouring copy's sphere."""
+    m = len(xp)
+    i = rows[:, 0].astype(np.int64)
+    q = rows[:, 1].astype(np.int64)
+    sphere = q >= 0
+    qq = np.where(sphere, q, 0)
+    d = xp[qq] - xp[i]
+    sx = np.where(d[:, 0] > 0.5 * edge, -1, np.where(d[:, 0] < -0.5 * edge, 1, 0))
+    sz = np.where(d[:, 2] > 0.5 * edge, -1, np.where(d[:, 2] < -0.5 * edge, 1, 0))
+    ix, iz = np.meshgrid(np.arange(cx), np.arange(cz), indexing="ij")
+    ix, iz = ix.ravel()[:, None], iz.ravel()[:, None]
+    copy = ix * cz + iz
+    pcopy = ((ix + sx[None, :]) % cx) * cz + (iz + sz[None, :]) % cz
+    owner = (copy * m + i[None, :]).ravel()
+    partner = np.where(sphere[None, :], pcopy * m + qq[None, :], q[None, :]).ravel()
+    ncopy = cx * cz
+    return (owner, partner, np.tile(rows[:, 2:5], (ncopy, 1)), np.tile(rows[:, 5], ncopy))
+
+
 def _patch_bed(rng, name, n_bed, Lx, Lz):
     """Copies of a settled periodic patch over the box, shifted by a seeded
-    offset in x and z (a translation of a periodic bed is a settled bed)."""
+    offset in x and z (a translation of a periodic bed is a settled bed);
+    also returns the tiled contact history (or None)."""
     xp, edge = load_patch(name)
     cx, cz = Lx / edge, Lz / edge
     if abs(cx - round(cx)) > 1e-12 or abs(cz - round(cz)) > 1e-12:
@@ -159,7 +196,28 @@ def _patch_bed(rng, name, n_bed, Lx, Lz):
     shift = rng.uniform(0.0, 1.0, size=2) * np.array([Lx, Lz])
     x[:, 0] = np.mod(x[:, 0] + shift[0], Lx)
     x[:, 2] = np.mod(x[:, 2] + shift[1], Lz)
-    return x
+    rows = load_patch_history(name)
+    hist = None if rows is None else _tile_history(xp, edge, rows, cx, cz)
+    return x, hist
+
+
+def _history_arrays(n, owner, partner, dt, uin):
+    """Contact history in the step's layout: slots of each sphere ordered by
+    partner ascending, then the bottom wall."""
+    key = np.where(partner >= 0, partner, np.int64(1) << 40)
+    order = np.lexsort((key, owner))
+    owner, partner, dt, uin = owner[order], partner[order], dt[order], uin[order]
+    count = np.bincount(owner, minlength=n)
+    if count.max(initial=0) > SLOTS:
+        raise ValueError("more contacts on a sphere than history slots")
+    first = np.concatenate([[0], np.cumsum(count)[:-1]])
+    slot = np.arange(len(owner)) - first[owner]
+    H = dict(partner=np.zeros((n, SLOTS), np.int32), delta_t=np.zeros((n, SLOTS, 3)),
+             u_in=np.zeros((n, SLOTS)), count=count.astype(np.int8))
+    H["partner"][owner, slot] = partner
+    H["delta_t"][owner, slot] = dt
+    H["u_in"][owner, slot] = uin
+    return H
 
 
 def _rsa(rng, n, Lx, Lz, y_lo, y_hi, D, min_sep=1.001):
@@ -213,14 +271,19 @@ class Bed:
     u: np.ndarray      # [n, 3] float64 translational velocities
     om: np.ndarray     # [n, 3] float64 angular velocities
     bed_top: float     # max y of bed spheres + R
+    # contact history at rest of a settled bed in the step's layout (dict of
+    # partner [n][SLOTS] int32, delta_t [n][SLOTS][3], u_in [n][SLOTS],
+    # count [n] int8, caller order), or None
+    hist: Optional[dict] = None
 
 
 def make_bed(w: Workload, seed: Optional[int] = None) -> Bed:
     rng = np.random.default_rng(w.seed if seed is None else seed)
     D = PHYS["D"]
     Lx, Ly, Lz = w.domain
+    hb = None
     if w.bed:
-        xb = _patch_bed(rng, w.bed, w.n_bed, Lx, Lz)
+        xb, hb = _patch_bed(rng, w.bed, w.n_bed, Lx, Lz)
     else:
         xb = _lattice_bed(rng, w.n_bed, Lx, Lz, D)
     top = float(xb[:, 1].max() + 0.5 * D) if w.n_bed else 0.0
@@ -237,8 +300,15 @@ def make_bed(w: Workload, seed: Optional[int] = None) -> Bed:
     om = rng.normal(0.0, om_bed, size=(w.n, 3))
     om[w.n_bed:] = rng.normal(0.0, w.omega_std, size=(w.n_upper, 3))
     perm = rng.permutation(w.n)   # callers see particles in no spatial order
+    hist = None
+    if hb is not None:
+        inv = np.empty(w.n, dtype=np.int64)
+        inv[perm] = np.arange(w.n)
+        owner, partner, dt, uin = hb
+        partner = np.where(partner >= 0, inv[np.maximum(partner, 0)], partner)
+        hist = _history_arrays(w.n, inv[owner], partner, dt, uin)
     return Bed(np.ascontiguousarray(x[perm]), np.ascontiguousarray(u[perm]),
-               np.ascontiguousarray(om[perm]), top)
+               np.ascontiguousarray(om[perm]), top, hist)
 
 
 def fcc_block(n_side: int, spacing: float, origin=(0.0, 0.0, 0.0)) -> np.ndarray:
@@ -277,6 +347,13 @@ def _loglaw(y, y_b, u_tau):
     return np.where(y > y_b, v, 0.0)
 
 
+def _bed_damping(y, y_b):
+    """Weight of the velocity fluctuation at height y: 1 above the bed top
+    y_b, falling linearly to 0 one diameter below it (the fluid inside a
+    settled bed moves with its spheres, which are at rest)."""
+    return np.clip((np.asarray(y, dtype=np.float64) - y_b) / PHYS["D"] + 1.0, 0.0, 1.0)
+
+
 def flow_modes(w: Workload, bed_top: float, seed: Optional[int] = None, n_modes: int = 32) -> FlowModes:
     rng = np.random.default_rng(10_000 + (w.seed if seed is None else seed))
     Lx, Ly, Lz = w.domain
@@ -297,7 +374,7 @@ def flow_modes(w: Workload, bed_top: float, seed: Optional[int] = None, n_modes:
     acc = np.zeros(X.shape + (3,))
     for m in range(n_modes):
         s = np.sin(2 * math.pi * (kx[m] * X / Lx + kz[m] * Z / Lz) + phase[m]) * \
-            np.sin(math.pi * ky[m] * Y / Ly)
+            np.sin(math.pi * ky[m] * Y / Ly) * _bed_damping(Y, bed_top)
         acc += s[..., None] * amp[m]
     rms = math.sqrt(float((acc ** 2).sum(-1).mean()))
     top = float(_loglaw(np.array([Ly]), bed_top, u_tau)[0])
@@ -340,7 +417,9 @@ def fluid_field(w: Workload, modes: FlowModes, step: int = 0, device="cpu", dtyp
         zs = (torch.arange(k0, k0 + Nz, dtype=f64, device=dev) + o[2]) * h
         ax = 2 * math.pi * kx[None, :] * (xs[:, None] - modes.u_c * t) / Lx      # [Nx, m]
         az = 2 * math.pi * kz[None, :] * zs[:, None] / Lz + ph[None, :]         # [Nz, m]
-        sy = torch.sin(math.pi * ky[None, :] * ys[:, None] / Ly) * amp[None, :, c]  # [ny, m]
+        damp = torch.tensor(_bed_damping(ys.cpu().numpy(), modes.y_b), dtype=f64, device=dev)
+        sy = (torch.sin(math.pi * ky[None, :] * ys[:, None] / Ly) * amp[None, :, c] *
+              damp[:, None])                                                        # [ny, m]
         Bm = torch.cat([torch.sin(ax), torch.cos(ax)], dim=1).T.contiguous()     # [2m, Nx]
         cz, sz = torch.cos(az), torch.sin(az)
         if out is not None:

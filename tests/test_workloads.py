@@ -95,3 +95,45 @@ def test_seed_shifts_the_tiling():
     ha = np.sort(a.x[:, 1])[: w.n_bed]
     hb = np.sort(b.x[:, 1])[: w.n_bed]
     assert np.array_equal(ha, hb)
+
+
+def _pairs_of_history(h):
+    """Sphere pairs (i < j) and wall rows of a history in the step's layout."""
+    n = len(h["count"])
+    owner = np.repeat(np.arange(n), h["count"].astype(np.int64))
+    slot = np.concatenate([np.arange(c) for c in h["count"].astype(np.int64)]) if n else []
+    partner = h["partner"][owner, slot]
+    sp = partner >= 0
+    pairs = {(int(a), int(b)) for a, b in zip(owner[sp], partner[sp])}
+    walls = {int(a) for a in owner[partner == W.WALL_BOTTOM]}
+    return pairs, walls, h["count"]
+
+
+@pytest.mark.parametrize("w", [W.C1, W.C2], ids=["c1", "c2"])
+def test_bed_history_is_the_settled_contact_set(w):
+    """The tiled history at rest: symmetric, slots in the step's order, and
+    the contacts of the bed's positions (a contact within the last
+    settling substep's motion of touching may differ)."""
+    bed = W.make_bed(w)
+    h = bed.hist
+    assert h is not None
+    pairs, walls, count = _pairs_of_history(h)
+    assert all((b, a) in pairs for a, b in pairs)
+    # slots: partners ascending, then the bottom wall; unused slots zero
+    for i in np.flatnonzero(count):
+        p = h["partner"][i, : count[i]]
+        sp = p[p >= 0]
+        assert np.all(np.diff(sp) > 0) and np.all(p[len(sp):] == W.WALL_BOTTOM)
+        assert np.all(h["partner"][i, count[i]:] == 0)
+    Lx, Ly, Lz = w.domain
+    p = O.make_params(nx=int(round(Lx * 10)), ny=int(round(Ly * 10)), nz=int(round(Lz * 10)),
+                      h=0.1, R=0.5, use_cells=1)
+    rc, ref, _ = O.contacts(p, bed.x)
+    assert rc == 0
+    ref_pairs = {(int(a), int(b)) for a, b in ref if b >= 0}
+    ref_pairs |= {(b, a) for a, b in ref_pairs}
+    ref_walls = {int(a) for a, b in ref if b == -1}
+    diff = len(pairs ^ ref_pairs) + len(walls ^ ref_walls)
+    assert diff <= 0.002 * (len(ref_pairs) + len(ref_walls)), diff
+    # the settled bed has no initial velocities
+    assert w.bed_u_std > 0 or np.count_nonzero(bed.u[bed.x[:, 1] < bed.bed_top - 0.5 + 1e-9]) == 0
