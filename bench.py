@@ -260,11 +260,14 @@ def learned_comparison(P, W, w, bed, torch, n_snap, K, tol=1e-6, max_iter=10):
     # a looser tolerance, reached by both forms
     a, _ = form("fp64_plain_1e-2", P.F64, False, 1e-2, max_iter)
     b, _ = form("fp32_learned_1e-2", P.F32, True, 1e-2, max_iter)
+    c, _ = form("fp32_plain_1e-2", P.F32, False, 1e-2, max_iter)
     res["to_1e-2"] = {"fp64_plain_ms": a["ms_per_step"], "fp64_plain_iterations": a["iterations"],
+                      "fp32_plain_ms": c["ms_per_step"], "fp32_plain_iterations": c["iterations"],
                       "fp32_learned_ms": b["ms_per_step"],
                       "fp32_learned_iterations": b["iterations"],
-                      "speedup": a["ms_per_step"] / b["ms_per_step"]}
-    for k in ("fp64_plain_1e-2", "fp32_learned_1e-2"):
+                      "speedup": a["ms_per_step"] / b["ms_per_step"],
+                      "learned_vs_fp32_plain": c["ms_per_step"] / b["ms_per_step"]}
+    for k in ("fp64_plain_1e-2", "fp32_learned_1e-2", "fp32_plain_1e-2"):
         res.pop(k, None)
     # accuracy: F_h of each form against FP64 plain run to 60 iterations
     ref, Fh_ref = form("fp64_plain_60", P.F64, False, 1e-12, 60)
