@@ -985,7 +985,9 @@ __device__ inline void spread_visit_v(const Geom &G, const int d[3], const T fo[
     if (!((unsigned)bx <= lim[0] && (unsigned)by <= lim[1] && (unsigned)bz <= lim[2])) continue;
     // the stencil's first row and plane in tile coordinates (-2 .. T - 1)
     const int y0 = by - kGuard, z0 = bz - kGuard;
-    A_t *Ac = acc + c * NODES + bx;
+    // the stencil's first row (it may lie outside the tile; only rows inside
+    // are written): one multiply per component, the rows at constant offsets
+    A_t *A0 = acc + c * NODES + bx + (z0 * PZ + y0 * PX);
     using W_t = typename std::conditional<std::is_integral<A_t>::value, T, A_t>::type;
     const W_t val = (W_t)(v[c] * scale);
     const T *wx = w[0][ox], *wy = w[1][oy], *wz = w[2][oz];
@@ -997,7 +999,7 @@ __device__ inline void spread_visit_v(const Geom &G, const int d[3], const T fo[
       for (int jj = 0; jj < 3; ++jj) {
         if ((unsigned)(y0 + jj) >= (unsigned)TY) continue;
         const W_t vzy = vz * (W_t)wy[jj];
-        A_t *row = Ac + (z0 + kk) * PZ + (y0 + jj) * PX;
+        A_t *row = A0 + (kk * PZ + jj * PX);   // constant offsets from A0
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
           if constexpr (std::is_integral<A_t>::value)
@@ -1096,8 +1098,10 @@ __device__ inline void tile_flush(const Geom &G, const A_t *acc, int i0, int j0,
     wall = c == 1 && (j == 0 || j == G.ny);
     a = (acc && !wall) ? acc[c * NODES + lz * PZ + ly * PX + lx + kGuard] : (A_t)0;
     if (wall ? !overwrite : (a == (A_t)0 && !poison && !overwrite)) return false;
-    g = (c == 1 ? base_v : base_uw) + (size_t)dz * ((size_t)nyc * (size_t)G.nx);
-    Fp = c == 0 ? f0 : (c == 1 ? f1 : f2);
+    // the row's plane offset is the same for every lane (c and dz depend on
+    // q only): it goes into the pointer, the lane's own base into the index
+    g = c == 1 ? base_v : base_uw;
+    Fp = (c == 0 ? f0 : (c == 1 ? f1 : f2)) + (size_t)dz * ((size_t)nyc * (size_t)G.nx);
     return true;
   };
   // the reads of f of a batch of the lane's rows first, so they are in
