@@ -206,8 +206,22 @@ __device__ inline void lds_load4(const void *src, void *wave_base) {
 // Waits until this wave's memory operations have completed.
 __device__ inline void wait_loads() { __builtin_amdgcn_s_waitcnt(0); }
 
-template <typename T, int MODE, int NB>
-__global__ __launch_bounds__(1024) void k_interp(
+// K: markers a lane.  With K = 2 (single-precision MDF passes only) lane t
+// takes the lane slots t and t + blockDim: a sphere needs half the waves,
+// so with one brick buffer about twice as many spheres are resident on a
+// compute unit (a unit holds 32 waves; five-wave spheres left six of them
+// in flight), and the per-sphere work is shared by twice the markers.  The
+// second marker's terms are added in the lane before the wave sums.
+constexpr int kSlotsK2 = 5;
+#ifndef PRS_INTERP_K2
+#define PRS_INTERP_K2 1
+#endif
+#ifndef PRS_INTERP_K2_WAVES
+#define PRS_INTERP_K2_WAVES 6
+#endif   // chunk slots a lane with K = 2 (784 chunks / 192 lanes at D/h = 10)
+template <typename T, int MODE, int NB, int K = 1>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(K == 2 ? PRS_INTERP_K2_WAVES : 1)))
+void k_interp(
     Geom G, const double *__restrict__ templ, const T *__restrict__ tm, const T *__restrict__ a0,
     const T *__restrict__ a1, const T *__restrict__ a2, const T *__restrict__ b0,
     const T *__restrict__ b1, const T *__restrict__ b2, double adt, double inv_adt,
@@ -225,8 +239,13 @@ __global__ __launch_bounds__(1024) void k_interp(
   const int wave_base = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;   // scalar
   const int p = xcd_item(blockIdx.x, n);
   if (p < 0) return;
+  static_assert(K == 1 || (K == 2 && MODE == kInterpMDF && sizeof(T) == 4),
+                "two markers a lane in the single-precision MDF pass only");
   const bool active = (int)threadIdx.x < G.nl;
   const int l = active ? order[threadIdx.x] : 0;
+  // the second marker of the lane (K = 2)
+  const bool active2 = K == 2 && (int)threadIdx.x + bdim < G.nl;
+  const int l2 = active2 ? order[threadIdx.x + bdim] : 0;
   const size_t N = (size_t)n;
 
   // the sphere's node, staggered fractions and brick origin (the rest of
@@ -257,6 +276,8 @@ __global__ __launch_bounds__(1024) void k_interp(
   const bool f_only = MODE == kInterpMDF && b0 != nullptr;
   T mhi[3] = {0, 0, 0}, mlo[3] = {0, 0, 0};
   if (active) MarkerOffset<T>::load(tm, threadIdx.x, mhi, mlo);   // tm in lane order
+  T mhi2[3] = {0, 0, 0}, mlo2[3] = {0, 0, 0};
+  if (K == 2 && active2) MarkerOffset<T>::load(tm, threadIdx.x + bdim, mhi2, mlo2);
 
   constexpr int VEC = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
@@ -284,7 +305,7 @@ __global__ __launch_bounds__(1024) void k_interp(
   // slot in use), and the chunk's element offset (k ny + j) nx + x0 in the
   // u and w arrays; in the v array (ny + 1 rows a plane) it is k nx more.
   // Element offsets fit 32 bits (a component holds fewer than 2^32 nodes).
-  constexpr int kSlots = BrickSlots<T>::value;
+  constexpr int kSlots = K == 1 ? BrickSlots<T>::value : kSlotsK2;
   constexpr unsigned kFuw = 1u << 28, kFv = 1u << 29, kFseam = 1u << 30, kFuse = 1u << 31;
   unsigned sK[kSlots];
   unsigned sOff[kSlots];
@@ -362,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_interp(
       *reinterpret_cast<vec_t *>(brick + row * P + ch * VEC) = v;
     }
   };
-  T U[3] = {(T)0, (T)0, (T)0};
+  T U[3] = {(T)0, (T)0, (T)0}, U2[3] = {(T)0, (T)0, (T)0};
   // Single-precision MDF passes over f read the recorded I[u-hat] through
   // LDS (loaded while the last stencils run) when the bricks are double
   // buffered.
@@ -410,15 +431,14 @@ __global__ __launch_bounds__(1024) void k_interp(
   // Component c interpolated from its brick: the three axis stencils, then
   // the 27-point sum contracted separably (x, then y, then z).  Selects
   // rather than indexing by c keep the arrays in registers.
-  auto stencil_component = [&](int c, const T *buf) {
-    if (!active) return;
+  auto stencil_one = [&](int c, const T *buf, const T mh[3], const T ml[3], T Uo[3]) {
     T wx[3], wy[3], wz[3];
     const T f0 = c == 0 ? fo[0][0] : fo[0][1];   // fo[0][stag(c, 0)]
     const T f1 = c == 1 ? fo[1][0] : fo[1][1];   // fo[1][stag(c, 1)]
     const T f2 = c == 2 ? fo[2][0] : fo[2][1];   // fo[2][stag(c, 2)]
-    const int bx = min(max(stencil_axis<T>(f0, mhi[0], mlo[0], wx) - 1 + E, 0), nb - 3);
-    const int by = min(max(stencil_axis<T>(f1, mhi[1], mlo[1], wy) - 1 + E, 0), nb - 3);
-    const int bz = min(max(stencil_axis<T>(f2, mhi[2], mlo[2], wz) - 1 + E, 0), nb - 3);
+    const int bx = min(max(stencil_axis<T>(f0, mh[0], ml[0], wx) - 1 + E, 0), nb - 3);
+    const int by = min(max(stencil_axis<T>(f1, mh[1], ml[1], wy) - 1 + E, 0), nb - 3);
+    const int bz = min(max(stencil_axis<T>(f2, mh[2], ml[2], wz) - 1 + E, 0), nb - 3);
     const T *bk = buf + ((bz * nb + by) * P + bx);
     T zsum = 0;
 #pragma unroll
@@ -432,9 +452,13 @@ __global__ __launch_bounds__(1024) void k_interp(
       }
       zsum = fma(wz[kk], ysum, zsum);
     }
-    U[0] = c == 0 ? zsum : U[0];
-    U[1] = c == 1 ? zsum : U[1];
-    U[2] = c == 2 ? zsum : U[2];
+    Uo[0] = c == 0 ? zsum : Uo[0];
+    Uo[1] = c == 1 ? zsum : Uo[1];
+    Uo[2] = c == 2 ? zsum : Uo[2];
+  };
+  auto stencil_component = [&](int c, const T *buf) {
+    if (active) stencil_one(c, buf, mhi, mlo, U);
+    if (K == 2 && active2) stencil_one(c, buf, mhi2, mlo2, U2);
   };
   // When the lane's slots cover the brick: direct loads into two LDS
   // buffers, the next component's brick in flight while the current one's
@@ -552,6 +576,12 @@ __global__ __launch_bounds__(1024) void k_interp(
   const double Ud[3] = {up[0] + (wp[1] * rl[2] - wp[2] * rl[1]),
                         up[1] + (wp[2] * rl[0] - wp[0] * rl[2]),
                         up[2] + (wp[0] * rl[1] - wp[1] * rl[0])};
+  double rl2[3] = {0, 0, 0};
+  if (K == 2 && active2)
+    for (int a = 0; a < 3; ++a) rl2[a] = G.h * ((double)mhi2[a] + (double)mlo2[a]);
+  const double Ud2[3] = {up[0] + (wp[1] * rl2[2] - wp[2] * rl2[1]),
+                         up[1] + (wp[2] * rl2[0] - wp[0] * rl2[2]),
+                         up[2] + (wp[0] * rl2[1] - wp[1] * rl2[0])};
 
   if (MODE != kInterpPlain && active && u0) {
     const size_t M = N * G.nl, m = (size_t)p * G.nl + l;
@@ -561,6 +591,13 @@ __global__ __launch_bounds__(1024) void k_interp(
       for (int c = 0; c < 3; ++c) U[c] = u0[c * M + m] + tadt * U[c];
     else
       for (int c = 0; c < 3; ++c) u0[c * M + m] = U[c];
+  }
+  if (K == 2 && active2 && u0) {
+    const size_t M = N * G.nl, m2 = (size_t)p * G.nl + l2;
+    if (f_only)
+      for (int c = 0; c < 3; ++c) U2[c] = u0[c * M + m2] + tadt * U2[c];
+    else
+      for (int c = 0; c < 3; ++c) u0[c * M + m2] = U2[c];
   }
 
   if (MODE == kInterpPlain) {
@@ -659,6 +696,20 @@ __global__ __launch_bounds__(1024) void k_interp(
       }
     }
   }
+  if (K == 2 && active2) {
+    // the lane's second marker (MDF), added to the first one's terms
+    const size_t M = N * G.nl, m2 = (size_t)p * G.nl + l2;
+    double d[3];
+    for (int c = 0; c < 3; ++c) {
+      const T res = (T)Ud2[c] - U2[c];
+      const T corr = res * inv_tadt;
+      out[c * M + m2] = corr;
+      vm = max(vm, abs_bits((float)corr));
+      d[c] = (double)corr;
+      red.v[kColSlip] += (double)res * (double)res;
+    }
+    red_add_ft(red, rl2, d);
+  }
   __shared__ float s_vmax[16];
   constexpr bool kForce = MODE == kInterpMDF || MODE == kInterpLearned;
   if (kForce) {
@@ -731,6 +782,27 @@ hipError_t launch_interp_mdf(hipStream_t s, const Geom &G, const Scratch &S, con
                                             nullptr, adt, S.xs[0], S.us[0], S.ws[0], n, nullptr,
                                             nullptr, S.slip_part, nullptr, LearnArgs{}, nullptr,
                                             (T *)S.u0);
+  const int nb = brick_edge(G.R, G.h);
+  if (PRS_INTERP_K2 && sizeof(T) == 4 && n > 0 && (nb == 14 || nb == 20)) {
+    // two markers a lane, one brick buffer
+    const int block = block_for((G.nl + 1) / 2);
+    const int P = brick_pitch_c<T>(nb);
+    if ((size_t)nb * nb * (P / (16 / sizeof(T))) <= (size_t)kSlotsK2 * block) {
+      const size_t lds = brick_bytes(nb, sizeof(T));
+      const T *tm = (const T *)S.tm32_lane;
+      const double inv_adt = adt != 0.0 ? 1.0 / adt : 0.0;
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(xcd_grid(n)), dim3(block), lds, s, G, S.templ, tm, uh[0],
+                           uh[1], uh[2], f[0], f[1], f[2], adt, inv_adt, S.xs[0], S.us[0],
+                           S.ws[0], n, nb, (T *)S.dF, (T *)nullptr, S.slip_part, S.ft_part,
+                           S.lane_order, LearnArgs{}, S.vmax, (T *)S.u0, 1);
+        return hipGetLastError();
+      };
+      if constexpr (sizeof(T) == 4)
+        return nb == 14 ? go(k_interp<float, kInterpMDF, 14, 2>)
+                        : go(k_interp<float, kInterpMDF, 20, 2>);
+    }
+  }
   return launch_interp_any<T, kInterpMDF>(s, G, S, uh[0], uh[1], uh[2], f[0], f[1], f[2], adt,
                                           S.xs[0], S.us[0], S.ws[0], n, (T *)S.dF, nullptr,
                                           S.slip_part, S.ft_part, LearnArgs{}, S.vmax,

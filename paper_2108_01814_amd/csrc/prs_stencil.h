@@ -114,6 +114,15 @@ __device__ inline void red_set_ft(Red &r, const double rl[3], const double d[3])
   r.v[5] = rl[0] * d[1] - rl[1] * d[0];
 }
 
+__device__ inline void red_add_ft(Red &r, const double rl[3], const double d[3]) {
+  r.v[0] += d[0];
+  r.v[1] += d[1];
+  r.v[2] += d[2];
+  r.v[3] += rl[1] * d[2] - rl[2] * d[1];
+  r.v[4] += rl[2] * d[0] - rl[0] * d[2];
+  r.v[5] += rl[0] * d[1] - rl[1] * d[0];
+}
+
 // Wave sums of eight columns at once, each step halving the columns a lane
 // carries: a lane keeps one half and adds its partner's copy of that half
 // (partners differ in lane bit 0, then bit 1), so the last four steps move
