@@ -1432,6 +1432,44 @@ __attribute__((amdgpu_waves_per_eu(kRecordOnly ? kRecordWaves : TileWaves<T>::va
   }
   if constexpr (!kRecordOnly) acc_clear<A_t, 3 * NODES>(acc);
   __syncthreads();
+  if constexpr (kRecordOnly) {
+    // Each wave walks whole candidates' marker ranges, 64 markers a round,
+    // and appends the survivors straight to the tile's record (an LDS
+    // counter places each wave's ballot): no search of the flattened
+    // (candidate, marker) index and no block-wide rounds.  The entries'
+    // order follows the waves' timing; the single-precision replay adds
+    // fixed-point integers, whose sums do not depend on it.
+    if (record && nc <= tc.cap) {
+      const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+      for (int sidx = threadIdx.x >> 6; sidx < nc; sidx += nw) {
+        const int cnt = c_pref[sidx], l0 = c_l0[sidx], k = c_idx[sidx];
+        const double cx = xs[k], cy = xs[N + k], cz = xs[2 * N + k];
+        for (int o = lane; o < ((cnt + 63) & ~63); o += 64) {
+          bool pass = false;
+          if (o < cnt) {
+            const int l = l0 + o;
+            const double X0 = cx + R * templ[3 * l], X1 = cy + R * templ[3 * l + 1],
+                         X2 = cz + R * templ[3 * l + 2];
+            pass = fabs(min_image(X0 - mctr[0], G.Lx)) <= mhw[0] &&
+                   fabs(X1 - mctr[1]) <= mhw[1] && fabs(min_image(X2 - mctr[2], G.Lz)) <= mhw[2];
+          }
+          const unsigned long long ball = __ballot(pass);
+          if (!ball) continue;
+          int wbase = 0;
+          if (lane == 0) wbase = atomicAdd(&r_len, __popcll(ball));
+          wbase = __shfl(wbase, 0);
+          const int pos = wbase + __popcll(ball & ((1ull << lane) - 1ull));
+          if (pass && pos < tc.cap) reg[pos] = ((unsigned)sidx << 10) | (unsigned)(l0 + o);
+        }
+      }
+    }
+    __syncthreads();
+    if (record && threadIdx.x == 0) {
+      tc.count[tile] = (nc <= tc.cap && r_len <= tc.cap) ? r_len - nc : -1;
+      tc.ncand[tile] = nc;
+    }
+    return;
+  }
   // exclusive scan of the range lengths (kTileCand entries, one per lane of
   // the first kTileCand threads): shuffles inside each wave, then the wave
   // totals
