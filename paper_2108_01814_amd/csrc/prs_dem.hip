@@ -74,7 +74,7 @@ __global__ void k_candidates(Cells C, Geom G, const int *__restrict__ start,
   int key[kCandCap];
   int cnt = 0;
   bool over = false;
-  for_each_near(C, G, start, pk, 1, 12, j, cut2, [&](int k) {
+  for_each_near(C, G, start, pk, 1, PRS_PK_SPLIT ? 4 : 12, j, cut2, [&](int k) {
     if (cnt < kCandCap) {
       const int id = perm[k];
       int c = cnt - 1;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_substep(
     uint32_t touching = 0;
 #pragma unroll 4
     for (int a = 0; a < nk; ++a) {
-      const double *q = pk + 12 * (size_t)cand[a * N + j];
+      const double *q = pk + pk_pos((size_t)cand[a * N + j], N);
       const double dx = min_image(q[0] - xp[0], G.Lx);
       const double dy = q[1] - xp[1];
       const double dz = min_image(q[2] - xp[2], G.Lz);
@@ -223,18 +223,19 @@ __global__ __launch_bounds__(256) void k_substep(
     for (; touching; touching &= touching - 1u) {
       const int a = __builtin_ctz(touching);
       const int k = cand[a * N + j];
-      const double *q = pk + 12 * (size_t)k;
+      const double *q = pk + pk_pos((size_t)k, N);
+      const double *qv = pk + pk_vel((size_t)k, N);   // u at +0, omega at +4
       const double dx = min_image(q[0] - xp[0], G.Lx);
       const double dy = q[1] - xp[1];
       const double dz = min_image(q[2] - xp[2], G.Lz);
       const double d2 = (dx * dx + dy * dy) + dz * dz;
       const double dist = sqrt(d2);
       const double nrm[3] = {dx / dist, dy / dist, dz / dist};
-      const double sw[3] = {wp[0] + q[8], wp[1] + q[9], wp[2] + q[10]};
+      const double sw[3] = {wp[0] + qv[4], wp[1] + qv[5], wp[2] + qv[6]};
       const double wxn[3] = {sw[1] * nrm[2] - sw[2] * nrm[1], sw[2] * nrm[0] - sw[0] * nrm[2],
                              sw[0] * nrm[1] - sw[1] * nrm[0]};
-      const double ucp[3] = {(up[0] - q[4]) + R * wxn[0], (up[1] - q[5]) + R * wxn[1],
-                             (up[2] - q[6]) + R * wxn[2]};
+      const double ucp[3] = {(up[0] - qv[0]) + R * wxn[0], (up[1] - qv[1]) + R * wxn[1],
+                             (up[2] - qv[2]) + R * wxn[2]};
       emit(perm[k], nrm, 2.0 * R - dist, ucp, false);
       ++my_pp;
     }
@@ -268,9 +269,9 @@ __global__ __launch_bounds__(256) void k_substep(
       xd[a * N + j] = xp[a];
       ud[a * N + j] = up[a];
       wd[a * N + j] = wp[a];
-      pd[12 * (size_t)j + a] = xp[a];
-      pd[12 * (size_t)j + 4 + a] = up[a];
-      pd[12 * (size_t)j + 8 + a] = wp[a];
+      pd[pk_pos(j, N) + a] = xp[a];
+      pd[pk_vel(j, N) + a] = up[a];
+      pd[pk_vel(j, N) + 4 + a] = wp[a];
     }
     if (!(xp[1] >= 0.0 && xp[1] <= G.Ly)) fl |= kFlagDomain;
     if (fl) atomicOr(status, fl);

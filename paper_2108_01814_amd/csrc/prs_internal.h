@@ -71,9 +71,11 @@ struct Scratch {
   size_t scan_tmp_elems;
   // sorted sphere state, double-buffered SoA [3][n]
   double *xs[2], *us[2], *ws[2], *x0;
-  // the same state packed per sphere, [n][12] = x, 0, u, 0, omega, 0 (with
-  // one pad after each triple), double-buffered like xs: the substeps'
-  // gathers of a partner's state touch one or two cache lines, not nine
+  // the same state packed per sphere, double-buffered like xs: positions
+  // [n][4] (x, 0), then velocities [n][8] (u, 0, omega, 0) -- the substeps'
+  // gathers of a partner's state touch one or two cache lines, not nine,
+  // and the contact test's gathers of positions four spheres a 128-byte line
+  // (see PkPos / PkVel)
   double *pk[2];
   double *fh, *th;            // [3][n] sorted
   double *ft_acc;             // [12][n]: (sum, compensation) x (Fx Fy Fz Tx Ty Tz)
@@ -110,6 +112,16 @@ struct Scratch {
   double *tm64_lane;
   int *lane_order;                // [nl]: marker handled by interpolation lane i
 };
+
+// Packed sphere state: sphere k's position (3 doubles) and its velocity and
+// angular velocity (at +0 and +4) in an array of 12 n doubles.
+#ifndef PRS_PK_SPLIT
+#define PRS_PK_SPLIT 1
+#endif
+__host__ __device__ inline size_t pk_pos(size_t k, size_t n) { return PRS_PK_SPLIT ? 4 * k : 12 * k; }
+__host__ __device__ inline size_t pk_vel(size_t k, size_t n) {
+  return PRS_PK_SPLIT ? 4 * n + 8 * k : 12 * k + 4;
+}
 
 // Learned warm start: the network's device buffers and, for the feature
 // pass, the output array and the sorted-to-caller permutation.

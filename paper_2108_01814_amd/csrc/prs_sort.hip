@@ -165,9 +165,9 @@ __global__ void k_gather_state(const int *__restrict__ perm, int n, Geom G,
     if (!isfinite(uv) || !isfinite(wv)) fl |= kFlagNonFinite;
     us[a * (size_t)n + j] = uv;
     ws[a * (size_t)n + j] = wv;
-    pk[12 * (size_t)j + a] = v;
-    pk[12 * (size_t)j + 4 + a] = uv;
-    pk[12 * (size_t)j + 8 + a] = wv;
+    pk[pk_pos(j, n) + a] = v;
+    pk[pk_vel(j, n) + a] = uv;
+    pk[pk_vel(j, n) + 4 + a] = wv;
   }
   int c = hc[i];
   if (c < 0 || c > kSlots) {
