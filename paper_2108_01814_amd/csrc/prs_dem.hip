@@ -63,28 +63,32 @@ __device__ inline void for_each_near(const Cells &C, const Geom &G, const int *s
 // ---------------------------------------------------------------------------
 // collision search
 // ---------------------------------------------------------------------------
-// pk: the packed sphere state [n][12] (positions first).
-__global__ void k_candidates(Cells C, Geom G, const int *__restrict__ start,
-                             const int *__restrict__ perm, const double *__restrict__ pk, int n,
-                             double cut2, int *__restrict__ ncand, int *__restrict__ cand,
-                             uint32_t *status) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// pk: the packed sphere state (positions [n][4] first).  Each thread keeps
+// its sorted candidate list in its own LDS column (an array indexed at run
+// time in registers would live in scratch memory).
+constexpr int kCandThreads = 128;
+__global__ __launch_bounds__(kCandThreads) void k_candidates(
+    Cells C, Geom G, const int *__restrict__ start, const int *__restrict__ perm,
+    const double *__restrict__ pk, int n, double cut2, int *__restrict__ ncand,
+    int *__restrict__ cand, uint32_t *status) {
+  __shared__ int s_key[kCandCap][kCandThreads];
+  __shared__ int s_loc[kCandCap][kCandThreads];
+  const int t = threadIdx.x;
+  const int j = blockIdx.x * blockDim.x + t;
   if (j >= n) return;
-  int loc[kCandCap];
-  int key[kCandCap];
   int cnt = 0;
   bool over = false;
   for_each_near(C, G, start, pk, 1, PRS_PK_SPLIT ? 4 : 12, j, cut2, [&](int k) {
     if (cnt < kCandCap) {
       const int id = perm[k];
       int c = cnt - 1;
-      while (c >= 0 && key[c] > id) {
-        key[c + 1] = key[c];
-        loc[c + 1] = loc[c];
+      while (c >= 0 && s_key[c][t] > id) {
+        s_key[c + 1][t] = s_key[c][t];
+        s_loc[c + 1][t] = s_loc[c][t];
         --c;
       }
-      key[c + 1] = id;
-      loc[c + 1] = k;
+      s_key[c + 1][t] = id;
+      s_loc[c + 1][t] = k;
       ++cnt;
     } else {
       over = true;
@@ -92,13 +96,14 @@ __global__ void k_candidates(Cells C, Geom G, const int *__restrict__ start,
   });
   if (over) atomicOr(status, kFlagCand);
   ncand[j] = cnt;
-  for (int c = 0; c < cnt; ++c) cand[c * (size_t)n + j] = loc[c];
+  for (int c = 0; c < cnt; ++c) cand[c * (size_t)n + j] = s_loc[c][t];
 }
 
 hipError_t launch_candidates(hipStream_t s, const Scratch &S, const Cells &C, const Geom &G,
                              int n, double cut) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_candidates, dim3((n + 127) / 128), dim3(128), 0, s, C, G, S.start, S.perm,
+  hipLaunchKernelGGL(k_candidates, dim3((n + kCandThreads - 1) / kCandThreads), dim3(kCandThreads),
+                     0, s, C, G, S.start, S.perm,
                      S.pk[0], n, cut * cut, S.ncand, S.cand, S.status);
   return hipGetLastError();
 }
