@@ -304,6 +304,51 @@ def test_failed_step_leaves_state_untouched(P):
             assert int(H.count.abs().sum()) == 0
 
 
+def test_collision_search_capacity_boundary(P):
+    """The step's candidate list holds 32 partners within 2R + skin (sec. 3.5,
+    collision search).  On a simple cubic lattice of spacing 1.25 D (no
+    sphere touches another or a wall) an interior sphere has 6, 12, 8, 6 and
+    24 lattice neighbours at 1, sqrt 2, sqrt 3, 2 and sqrt 5 spacings: a cut
+    of 2.65 D keeps 32 of them (the step runs), a cut of 2.9 D keeps 56 (the
+    step stops with PRS_ECAPACITY and leaves the state as it was)."""
+    import torch
+
+    a = 1.25
+    ii, kk, jj = np.meshgrid(np.arange(8), np.arange(8), np.arange(5), indexing="ij")
+    x = np.stack([0.6 + a * ii.ravel(), 1.0 + a * jj.ravel(), 0.6 + a * kk.ravel()], axis=1)
+    w = W.small("lattice", 1, 0, (10.0, 9.0, 10.0))
+    Lx, _, Lz = w.domain
+
+    def most_candidates(cut):      # brute force over all pairs, periodic in x and z
+        d = x[None, :, :] - x[:, None, :]
+        d[..., 0] -= Lx * np.round(d[..., 0] / Lx)
+        d[..., 2] -= Lz * np.round(d[..., 2] / Lz)
+        r2 = (d * d).sum(axis=2)
+        np.fill_diagonal(r2, np.inf)
+        assert r2.min() > 1.0 + 1e-9                 # no contacts
+        return int((r2 < cut * cut).sum(axis=1).max())
+
+    assert most_candidates(2.65) == 32 and most_candidates(2.9) == 56
+    g0 = None
+    for skin, ok in ((1.65, True), (1.9, False)):
+        with P.Context(prs_params(P, w, P.F64, n=len(x), skin=skin)) as ctx:
+            if g0 is None:
+                g0 = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in ctx.grid_shapes()]
+            xd, ud, od = dev(x), dev(np.zeros_like(x)), dev(np.zeros_like(x))
+            H = P.History.zeros(len(x))
+            f = [torch.zeros_like(t) for t in g0]
+            if ok:
+                _, _, st = ctx.step(g0, f, xd, ud, od, H, zero_f=True)
+                assert st["contacts"] == 0 and int(H.count.abs().sum()) == 0
+                assert np.abs(xd.cpu().numpy() - x).max() < 0.1     # settled a little
+            else:
+                with pytest.raises(P.PrsError) as e:
+                    ctx.step(g0, f, xd, ud, od, H, zero_f=True)
+                assert e.value.code == P.PRS_ECAPACITY and "candidates" in str(e.value)
+                assert np.array_equal(xd.cpu().numpy(), x)
+                assert int(H.count.abs().sum()) == 0
+
+
 def test_empty_step(P):
     import torch
 
