@@ -252,6 +252,38 @@ def test_first_iteration_force_of_sphere_in_still_fluid(orc):
     assert np.allclose(out["Th"][0], expect_T, atol=1e-9 * np.abs(out["Fh"]).max())
 
 
+def test_step_feeds_its_forcing_to_the_particle_motion(orc):
+    """The whole step for one free sphere (no contacts), in closed form: the
+    forcing of a sphere moving with U through still fluid (one iteration,
+    F_h = -rho_f dV N_L U/(alpha dt)), then n_sub symplectic Euler substeps
+    of eqs. 7-8 with F_h, T_h and the buoyant weight held fixed:
+    u = U + n dt a, x = x0 + n dt U + dt^2 a n(n+1)/2, omega = n dt T_h/I,
+    a = (F_h + (rho_p - rho_f) V g)/m_p, dt = dt_f/n.  A dropped buoyancy,
+    a flipped F_h or an unused T_h fails it."""
+    p = params(orc, nx=24, ny=20, nz=24, nl=314, n_iter=1, rho_f=1.3, rho_p=2.1, alpha=0.5,
+               n_sub=7)
+    x0 = np.array([[1.2, 1.0, 1.1]])
+    U = np.array([[0.3, -0.2, 0.5]])
+    x, u, om = x0.copy(), U.copy(), np.zeros((1, 3))
+    g = [np.zeros(s) for s in orc.grid_shapes(p)]
+    f = [np.zeros(s) for s in orc.grid_shapes(p)]
+    rc, out = orc.step(p, g, f, x, u, om, orc.History(1))
+    assert rc == 0
+    t, dV = orc.template(p.nl, p.R, p.h)
+    Fh, Th = out["Fh"][0], out["Th"][0]
+    assert np.allclose(Fh, -p.rho_f * dV * p.nl * U[0] / (p.alpha * p.dt_f), rtol=1e-12)
+    V = 4.0 / 3.0 * math.pi * p.R ** 3
+    m = p.rho_p * V
+    I = 0.4 * m * p.R ** 2
+    a = (Fh + (p.rho_p - p.rho_f) * V * np.array(p.g[:])) / m
+    n, dt = p.n_sub, p.dt_f / p.n_sub
+    assert np.allclose(u[0], U[0] + n * dt * a, rtol=0, atol=1e-12 * np.abs(u).max())
+    assert np.allclose(x[0], x0[0] + n * dt * U[0] + dt * dt * a * n * (n + 1) / 2, rtol=0,
+                       atol=1e-13)
+    assert np.allclose(om[0], n * dt * Th / I, rtol=1e-12, atol=1e-300)
+    assert np.abs(om[0]).max() > 0       # the template's centroid offset gives a torque
+
+
 def test_force_field_sums_to_minus_particle_force(orc):
     """Momentum balance: the force given to the fluid equals minus the force
     on the particles, rho_f sum_n f_n h^3 = -sum_p F_h (interior spheres)."""
