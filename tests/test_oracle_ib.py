@@ -284,6 +284,32 @@ def test_step_feeds_its_forcing_to_the_particle_motion(orc):
     assert np.abs(om[0]).max() > 0       # the template's centroid offset gives a torque
 
 
+def test_step_with_a_contact_balances_momentum(orc):
+    """Two touching spheres (normal and tangential contact forces) through a
+    whole step: the contact forces cancel in pairs, so over the step the
+    pair's momentum changes by exactly (sum F_h + 2 (rho_p - rho_f) V g) dt_f,
+    with F_h the step's own forcing result."""
+    p = params(orc, nx=32, ny=24, nz=24, nl=314, n_iter=2, rho_f=1.0, rho_p=2.5, n_sub=9)
+    x = np.array([[1.0, 1.2, 1.2], [1.99, 1.2, 1.2]])
+    u = np.array([[0.2, 0.05, 0.0], [-0.1, 0.0, 0.03]])
+    om = np.array([[0.0, 0.0, 0.4], [0.1, 0.0, 0.0]])
+    u0 = u.copy()
+    g = [np.zeros(s) for s in orc.grid_shapes(p)]
+    f = [np.zeros(s) for s in orc.grid_shapes(p)]
+    H = orc.History(2)
+    rc, out = orc.step(p, g, f, x, u, om, H)
+    assert rc == 0 and H.cnt.tolist() == [1, 1]          # the pair stayed in contact
+    V = 4.0 / 3.0 * math.pi * p.R ** 3
+    m = p.rho_p * V
+    dP = m * (u - u0).sum(axis=0)
+    expect = (out["Fh"].sum(axis=0) + 2 * (p.rho_p - p.rho_f) * V * np.array(p.g[:])) * p.dt_f
+    assert np.abs(dP - expect).max() < 1e-12 * np.abs(m * u0).max()
+    # the contact did act: the spheres' relative velocity differs from what
+    # the hydrodynamic forces alone give
+    free = u0 + (out["Fh"] / m + (1 - p.rho_f / p.rho_p) * np.array(p.g[:])) * p.dt_f
+    assert np.abs((u - free)[0] - (u - free)[1]).max() > 1e-3
+
+
 def test_force_field_sums_to_minus_particle_force(orc):
     """Momentum balance: the force given to the fluid equals minus the force
     on the particles, rho_f sum_n f_n h^3 = -sum_p F_h (interior spheres)."""
