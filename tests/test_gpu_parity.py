@@ -304,6 +304,41 @@ def test_failed_step_leaves_state_untouched(P):
             assert int(H.count.abs().sum()) == 0
 
 
+@pytest.mark.parametrize("precision,rtol", [(1, 1e-12), (0, 1e-6)])
+def test_free_sphere_step_closed_form(P, precision, rtol):
+    """The library's whole step for one sphere moving with U through still
+    fluid, against closed forms (no oracle): one forcing iteration gives
+    F_h = -rho_f dV N_L U/(alpha dt_f) with dV = pi h (12 R^2 + h^2)/(3 N_L)
+    (sec. 2.1); the n_sub substeps then advance with F_h, T_h and the
+    buoyant weight held fixed (symplectic Euler, eqs. 7-8)."""
+    import torch
+
+    w = W.small("free", 1, 0, (4.0, 3.0, 4.0))
+    kw = dict(n_iter=1, alpha=0.5, rho_f=1.3, rho_p=2.1, n_sub=7)
+    x0 = np.array([[1.2, 1.0, 1.1]])
+    U = np.array([[0.3, -0.2, 0.5]])
+    with P.Context(prs_params(P, w, precision, n=1, **kw)) as ctx:
+        dt = torch.float64 if precision == 1 else torch.float32
+        g = [torch.zeros(s, dtype=dt, device="cuda") for s in ctx.grid_shapes()]
+        f = [torch.zeros_like(a) for a in g]
+        xd, ud, od = dev(x0), dev(U), dev(np.zeros((1, 3)))
+        Fh, Th, st = ctx.step(g, f, xd, ud, od, P.History.zeros(1), zero_f=True)
+        Fh, Th = Fh.cpu().numpy()[0], Th.cpu().numpy()[0]
+        x, u, om = xd.cpu().numpy()[0], ud.cpu().numpy()[0], od.cpu().numpy()[0]
+    R, h, nl, dt_f = 0.5, w.h, w.n_markers, W.PHYS["dt_f"]
+    dV = math.pi * h * (12 * R * R + h * h) / (3 * nl)
+    assert np.allclose(Fh, -kw["rho_f"] * dV * nl * U[0] / (kw["alpha"] * dt_f), rtol=rtol, atol=0)
+    V = 4.0 / 3.0 * math.pi * R ** 3
+    m = kw["rho_p"] * V
+    I = 0.4 * m * R * R
+    a = (Fh + (kw["rho_p"] - kw["rho_f"]) * V * np.array(W.PHYS["g"])) / m
+    n, ds = kw["n_sub"], dt_f / kw["n_sub"]
+    assert np.abs(u - (U[0] + n * ds * a)).max() < 1e-12
+    assert np.abs(x - (x0[0] + n * ds * U[0] + ds * ds * a * n * (n + 1) / 2)).max() < 1e-13
+    assert np.abs(om - n * ds * Th / I).max() < 1e-12 * max(1.0, np.abs(om).max())
+    assert st["contacts"] == 0
+
+
 def test_collision_search_capacity_boundary(P):
     """The step's candidate list holds 32 partners within 2R + skin (sec. 3.5,
     collision search).  On a simple cubic lattice of spacing 1.25 D (no
