@@ -208,7 +208,9 @@ def test_fcc_twelve_contacts_on_gpu(P):
 
 
 # ----------------------------------------------------------- whole step ---
-def run_pair(P, orc, w, precision, n_steps=1, **kw):
+def run_pair(P, orc, w, precision, n_steps=1, start_hist=False, **kw):
+    """One or more steps on both sides from the same seeded bed; with
+    start_hist, both start from the bed's stored contact history at rest."""
     import torch
 
     bed = W.make_bed(w)
@@ -216,7 +218,7 @@ def run_pair(P, orc, w, precision, n_steps=1, **kw):
     g = gpu_fields(f64, precision)
     x, u, om = dev(bed.x), dev(bed.u), dev(bed.om)
     with P.Context(prs_params(P, w, precision, **kw)) as ctx:
-        H = P.History.zeros(w.n)
+        H = P.History.from_host(bed.hist) if start_hist else P.History.zeros(w.n)
         f = [torch.zeros_like(a) for a in g]
         for _ in range(n_steps):
             Fh, Th, st = ctx.step(g, f, x, u, om, H, zero_f=True)
@@ -228,6 +230,11 @@ def run_pair(P, orc, w, precision, n_steps=1, **kw):
     uh = host64(g)
     xo, uo, oo = bed.x.copy(), bed.u.copy(), bed.om.copy()
     Ho = orc.History(w.n)
+    if start_hist:
+        Ho.partner[:] = bed.hist["partner"]
+        Ho.dt[:] = bed.hist["delta_t"]
+        Ho.uin[:] = bed.hist["u_in"]
+        Ho.cnt[:] = bed.hist["count"]
     for _ in range(n_steps):
         fo = [np.zeros_like(a) for a in uh]
         rc, out = orc.step(p, uh, fo, xo, uo, oo, Ho)
@@ -264,6 +271,25 @@ def test_step_parity(P, orc, precision, w):
     assert pp % 2 == 0 and pp > 0
     assert gpu["st"]["pairs_last"] == pp // 2
     assert gpu["st"]["wall_last"] == int(((ref["partner"] < 0) & used).sum())
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_step_parity_from_settled_history(P, orc, precision):
+    """The step as the benchmark runs it: the settled C1 bed starting from its
+    stored contact history (loaded tangential springs, inherited impact
+    velocities), on both sides."""
+    assert int(W.make_bed(W.C1).hist["count"].sum()) > 1000
+    gpu, ref = run_pair(P, orc, W.C1, precision, start_hist=True)
+    tol = TOL[precision]
+    assert rel_err(gpu["Fh"], ref["Fh"]) < tol
+    assert rel_err(gpu["Th"], ref["Th"]) < tol
+    assert np.abs(gpu["x"] - ref["x"]).max() < tol
+    assert rel_err(gpu["u"], ref["u"]) < tol
+    assert rel_err(gpu["om"], ref["om"]) < tol
+    assert np.array_equal(gpu["count"], ref["count"])
+    assert np.array_equal(gpu["partner"], ref["partner"])
+    assert rel_err(gpu["dt"], ref["dt"]) < max(tol, 1e-10)
+    assert rel_err(gpu["uin"], ref["uin"]) < max(tol, 1e-10)
 
 
 def test_two_steps_carry_history(P, orc):
